@@ -1,0 +1,232 @@
+/*
+ * tds.h - distance-threshold search over trajectory line segments on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Gowanlock & Casanova, "Parallel Distance Threshold Query
+ * Processing for Spatiotemporal Trajectory Databases on the GPU", Sec. 3):
+ * a database D of n line segments in 3 spatial dimensions + time, each with
+ * a start point (x,y,z,t)_start, an end point (x,y,z,t)_end and a trajectory
+ * id; the point moves linearly from start to end. Given query segments and a
+ * distance d per query segment, report every (query segment, entry segment,
+ * [t_a, t_b]) such that the two moving points are within Euclidean distance
+ * d at every time of [t_a, t_b], where [t_a, t_b] is the full set of such
+ * times inside the two segments' common time span.
+ *
+ * Method (Sec. 4 and Sec. 5, Alg. 1): entries sorted by t_start and grouped
+ * into m fixed-width temporal bins give each query segment a contiguous
+ * candidate index range; each candidate is compared with the query segment
+ * (temporal intersection, then the time interval within d from a degree-two
+ * polynomial) and hits are appended to a result buffer.
+ *
+ * Semantics shared by every entry point:
+ *  - Two spans are compared only when they overlap with positive length:
+ *    max(t_start) < min(t_end).
+ *  - "Within d" is closed (distance <= d); a tangency gives [t*, t*].
+ *  - The decision is taken in IEEE binary64 by one fixed expression, so the
+ *    hit set does not depend on launch shape, batch size, bin count or mode.
+ *  - Result order is unspecified; sort by (query_idx, entry_idx) to compare.
+ *
+ * Threading: an index is immutable after build and may be shared by several
+ * query handles on several streams. One query handle must not be used by
+ * two threads at once.
+ *
+ * Errors: every int-returning call returns TDS_OK (0) or a negative status;
+ * tds_last_error() gives a message for the calling thread's last failure.
+ */
+#ifndef TDS_H
+#define TDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDS_ABI_VERSION 1
+
+/* Status codes. */
+#define TDS_OK 0
+#define TDS_EINVAL (-1)    /* null pointer, n < 0, t_end <= t_start, non-finite value, d < 0, bad option */
+#define TDS_ENOMEM (-2)    /* device or host allocation failed */
+#define TDS_EDEVICE (-3)   /* a HIP call failed (message names it) */
+#define TDS_EOVERFLOW (-4) /* more hits than the result buffer after all retries */
+#define TDS_ESTATE (-5)    /* call out of order (e.g. fetch before a query) */
+
+/* Where the arrays of a tds_segments live. */
+#define TDS_MEM_HOST 0
+#define TDS_MEM_DEVICE 1
+
+/*
+ * Segments as a structure of arrays (Sec. 3): start point (x0,y0,z0,t0) and
+ * end point (x1,y1,z1,t1) of segment i are x0[i] ... t1[i]. All arrays hold n
+ * binary64 values and live in host or device memory as `mem` says. traj_id
+ * (optional, may be NULL: then the trajectory id is the segment's index) is
+ * copied into results. The caller keeps ownership; the library only reads
+ * the arrays during the call that receives them.
+ */
+typedef struct {
+    int64_t n;
+    int32_t mem;
+    int32_t reserved;
+    const double *x0, *y0, *z0, *t0;
+    const double *x1, *y1, *z1, *t1;
+    const int64_t *traj_id;
+} tds_segments;
+
+/* Index options (Sec. 4). num_bins: m >= 1 fixed-width temporal bins over
+ * [min t_start, max t_end] of the database. */
+typedef struct {
+    int32_t num_bins;
+    int32_t flags; /* reserved, 0 */
+} tds_index_opts;
+
+/* Query modes. */
+#define TDS_MODE_FP64 0         /* every candidate pair decided in binary64 */
+#define TDS_MODE_FP32_REFINE 1  /* binary32 conservative filter, binary64 decision of survivors */
+
+/* How query segments are grouped into tiles (batches, Sec. 6). */
+#define TDS_TILE_PERIODIC 0     /* consecutive runs of batch_size segments in t_start order ("Periodic") */
+#define TDS_TILE_RANGE 1        /* runs of <= batch_size segments with the same candidate bin range */
+
+/* Query flags. */
+#define TDS_QF_TIMING 1         /* record per-stage HIP event times (tds_stats.ms_*) */
+#define TDS_QF_COUNT_OVERLAP 2  /* the pair kernel also counts overlapping pairs it examined */
+
+typedef struct {
+    int32_t mode;        /* TDS_MODE_* */
+    int32_t tiling;      /* TDS_TILE_* */
+    int32_t batch_size;  /* query segments per tile, 1..4096; 0 = 128 */
+    int32_t block_size;  /* pair-kernel threads per workgroup: 64, 128, 256, 512 or 1024; 0 = 256 */
+    int32_t reserved0;   /* 0 (a work item is block_size x entries-per-lane candidates) */
+    int32_t max_retries; /* result-buffer regrowths allowed; < 0 = 4 */
+    int64_t capacity;    /* initial result capacity (hits); 0 = library default */
+    int32_t grid;        /* pair-kernel workgroups; 0 = library default */
+    int32_t flags;       /* TDS_QF_* */
+} tds_query_opts;
+
+/* One result (Sec. 3 and Alg. 1): indices are positions in the caller's
+ * arrays; entry_traj is the entry's trajectory id. */
+typedef struct {
+    int64_t query_idx;
+    int64_t entry_idx;
+    int64_t entry_traj;
+    double t_a;
+    double t_b;
+} tds_hit;
+
+typedef struct {
+    int64_t n_query;     /* query segments in the last batch */
+    int64_t n_eval;      /* candidate pairs examined: sum over tiles of segments x range */
+    int64_t n_overlap;   /* pairs with a common span of positive length (from the time arrays) */
+    int64_t n_overlap_k; /* the same, counted in the pair kernel (TDS_QF_COUNT_OVERLAP), else -1 */
+    int64_t n_refine;    /* FP32_REFINE: pairs passed to the binary64 decision; FP64: -1 */
+    int64_t n_hit;
+    int64_t n_tiles;
+    int64_t n_items;
+    int32_t retries;
+    int32_t grid;        /* pair-kernel workgroups used */
+    float ms_prep;       /* TDS_QF_TIMING: query preparation, sort and tiling */
+    float ms_pair;       /* pair kernel (last launch) */
+    float ms_fetch;      /* result translation + copy */
+    float reserved;
+} tds_stats;
+
+typedef struct {
+    int64_t n;           /* entries */
+    int32_t num_bins;    /* m as requested */
+    int32_t nonempty_bins;
+    double t_first;      /* min t_start */
+    double t_last;       /* max t_end */
+    double bin_width;    /* (t_last - t_first) / m */
+    int64_t device_bytes;
+} tds_index_info;
+
+/* One non-empty bin (Sec. 4): start = smallest t_start of its entries,
+ * end = largest t_end, [first, last] = its index range in t_start order,
+ * bin = its number j in 0..m-1. */
+typedef struct {
+    double start;
+    double end;
+    int64_t first;
+    int64_t last;
+    int64_t bin;
+} tds_bin;
+
+typedef struct tds_index tds_index;
+typedef struct tds_query tds_query;
+
+/*
+ * Build the index of a database (Sec. 4): entries sorted by non-decreasing
+ * t_start (ties in input order), m bins of width (t_last - t_first)/m with
+ * entry i in bin clamp(floor((t0_i - t_first)/width), 0, m-1), and per bin
+ * its start, end and index range. The sorted entries, their velocities and
+ * their binary32 boxes go to device memory and stay there. `db` may be in
+ * host or device memory; `stream` (a hipStream_t, NULL = default) orders the
+ * uploads, and the call returns after they are complete. Returns TDS_EINVAL
+ * for invalid segments, n == 0 is allowed (every query then has 0 hits).
+ */
+int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *stream,
+                    tds_index **out);
+int tds_index_info_get(const tds_index *ix, tds_index_info *out);
+/* Copy up to cap non-empty bins (in time order) to host memory; *n_out gets
+ * their number. */
+int tds_index_bins(const tds_index *ix, tds_bin *out, int64_t cap, int64_t *n_out);
+/* Release the index. Every query handle made from it must be destroyed first. */
+void tds_index_destroy(tds_index *ix);
+
+/*
+ * Compute bins from host arrays of t_start / t_end that are already sorted
+ * by t_start (no device needed): same rules as tds_build_index. Writes up to
+ * cap non-empty bins to out and their number to *n_out.
+ */
+int tds_plan_bins(const double *t0_sorted, const double *t1_sorted, int64_t n, int32_t num_bins,
+                  tds_bin *out, int64_t cap, int64_t *n_out);
+
+/*
+ * The candidate range of query segments (Sec. 4, host planning helper, no
+ * device needed): for each (t0[i], t1[i]) the bins whose temporal extent
+ * overlaps it with positive length, i.e. from the first bin whose running
+ * maximum end exceeds t0[i] to the last bin whose start is below t1[i];
+ * first[i]..last[i] is the union of their index ranges (last < first when
+ * empty). bins: the non-empty bins in time order, as tds_plan_bins or
+ * tds_index_bins give them.
+ */
+int tds_plan_ranges(const tds_bin *bins, int64_t nb, const double *t0, const double *t1,
+                    int64_t nq, int64_t *first, int64_t *last);
+
+/* A query handle owns the device buffers of one batch at a time (query
+ * records, tiles, result buffer); they grow on demand and are reused. */
+int tds_query_create(tds_index *ix, tds_query **out);
+void tds_query_destroy(tds_query *qh);
+
+/*
+ * Start the search of query segments q (with per-segment thresholds d[i] >= 0,
+ * n values, in the same memory space as q) against the index, on `stream`.
+ * Returns once the work is enqueued; inputs in device memory must stay valid
+ * until tds_fetch_results returns. Inputs in host memory are copied first.
+ * Invalid device-resident segments are reported by tds_fetch_results.
+ */
+int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
+                    const tds_query_opts *opts, void *stream);
+
+/*
+ * Wait for the batch, re-run the pair kernel with a larger result buffer if
+ * it overflowed (Sec. 5: re-attempt with more memory), translate to caller
+ * indices and write min(cap, n) records to `out` (host memory when out_mem is
+ * TDS_MEM_HOST, device memory for TDS_MEM_DEVICE). *n_total always receives
+ * the number of hits, so cap = 0 sizes the buffer.
+ */
+int tds_fetch_results(tds_query *qh, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total);
+int tds_query_stats(const tds_query *qh, tds_stats *out);
+/* After tds_fetch_results: the candidate range the device computed for each
+ * query segment of the last batch (caller order, host arrays of n values). */
+int tds_query_ranges(const tds_query *qh, int64_t *first, int64_t *last, int64_t n);
+
+const char *tds_last_error(void);
+int tds_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDS_H */

@@ -1,0 +1,272 @@
+"""Python binding of the C ABI: build_index / query_batch / fetch_results.
+
+Argument marshalling only. Inputs are numpy arrays (host memory) or torch
+float64 tensors on the GPU (device memory); every step of the search runs in
+the library's HIP kernels. torch is used for device buffers and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+FIELDS = ("x0", "y0", "z0", "t0", "x1", "y1", "z1", "t1")
+MODES = {"fp64": L.TDS_MODE_FP64, "fp32_refine": L.TDS_MODE_FP32_REFINE}
+TILINGS = {"periodic": L.TDS_TILE_PERIODIC, "range": L.TDS_TILE_RANGE}
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return torch.cuda.current_stream().cuda_stream or None
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _segments(seg, with_traj=True):
+    """tds_segments for an object with x0..t1 (and optionally traj) arrays."""
+    arrs = [getattr(seg, f) for f in FIELDS]
+    traj = getattr(seg, "traj", None) if with_traj else None
+    keep = []
+    if _is_torch(arrs[0]):
+        import torch
+        mem = L.TDS_MEM_DEVICE
+        ptrs = []
+        for a in arrs:
+            if a.dtype != torch.float64 or not a.is_cuda:
+                raise TypeError("device segments must be float64 CUDA tensors")
+            a = a.contiguous()
+            keep.append(a)
+            ptrs.append(a.data_ptr())
+        tptr = None
+        if traj is not None:
+            t = traj.to(device=arrs[0].device, dtype=torch.int64).contiguous()
+            keep.append(t)
+            tptr = t.data_ptr()
+        n = int(arrs[0].numel())
+    else:
+        mem = L.TDS_MEM_HOST
+        ptrs = []
+        for a in arrs:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            keep.append(a)
+            ptrs.append(a.ctypes.data)
+        tptr = None
+        if traj is not None:
+            t = np.ascontiguousarray(traj, dtype=np.int64)
+            keep.append(t)
+            tptr = t.ctypes.data
+        n = int(np.asarray(arrs[0]).shape[0])
+    s = L.tds_segments(n, mem, 0, *ptrs, tptr)
+    return s, keep, mem
+
+
+@dataclass
+class Hits:
+    """Search results in the caller's indices (numpy arrays or torch tensors)."""
+    query: object
+    entry: object
+    traj: object
+    ta: object
+    tb: object
+
+    def __len__(self):
+        return int(self.query.shape[0])
+
+    def sorted(self) -> "Hits":
+        """Host copy sorted by (query, entry)."""
+        h = self.numpy()
+        o = np.lexsort((h.entry, h.query))
+        return Hits(h.query[o], h.entry[o], h.traj[o], h.ta[o], h.tb[o])
+
+    def numpy(self) -> "Hits":
+        if _is_torch(self.query):
+            return Hits(*[x.cpu().numpy() for x in (self.query, self.entry, self.traj, self.ta, self.tb)])
+        return self
+
+
+class Index:
+    """A database resident on the GPU (tds_build_index)."""
+
+    def __init__(self, db, num_bins: int, stream=None):
+        s, keep, _ = _segments(db, with_traj=True)
+        opts = L.tds_index_opts(int(num_bins), 0)
+        h = C.c_void_p()
+        L.check(L.lib().tds_build_index(C.byref(s), C.byref(opts), _stream_handle(stream), C.byref(h)))
+        del keep
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = L.tds_index_info()
+        L.check(L.lib().tds_index_info_get(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in L.tds_index_info._fields_}
+
+    def bins(self) -> np.ndarray:
+        n = C.c_int64()
+        L.check(L.lib().tds_index_bins(self._h, None, 0, C.byref(n)))
+        out = (L.tds_bin * max(n.value, 1))()
+        L.check(L.lib().tds_index_bins(self._h, out, n.value, C.byref(n)))
+        return _bins_array(out, n.value)
+
+    def close(self):
+        if self._h:
+            L.lib().tds_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+BIN_DTYPE = np.dtype([("start", "f8"), ("end", "f8"), ("first", "i8"), ("last", "i8"), ("bin", "i8")])
+
+
+def _bins_array(cbins, n) -> np.ndarray:
+    return np.frombuffer(bytes(cbins)[: n * BIN_DTYPE.itemsize], dtype=BIN_DTYPE).copy()
+
+
+class Query:
+    """One query handle (tds_query_create): buffers reused across batches."""
+
+    def __init__(self, index: Index):
+        self.index = index
+        h = C.c_void_p()
+        L.check(L.lib().tds_query_create(index.handle, C.byref(h)))
+        self._h = h
+        self._keep = None
+        self._nq = 0
+
+    def batch(self, q, d, mode="fp64", tiling="periodic", batch_size=0, block_size=0,
+              capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False, stream=None):
+        s, keep, mem = _segments(q, with_traj=False)
+        if mem == L.TDS_MEM_DEVICE:
+            import torch
+            dd = d if _is_torch(d) else torch.as_tensor(np.broadcast_to(d, (s.n,)), dtype=torch.float64,
+                                                        device=q.x0.device)
+            dd = dd.to(torch.float64).contiguous()
+            if dd.numel() != s.n:
+                dd = dd.expand(s.n).contiguous()
+            dptr = dd.data_ptr()
+        else:
+            dd = np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.float64), (s.n,)))
+            dptr = dd.ctypes.data
+        keep.append(dd)
+        flags = (L.TDS_QF_TIMING if timing else 0) | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
+        o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,
+                             int(max_retries), int(capacity), int(grid), flags)
+        L.check(L.lib().tds_query_batch(self._h, C.byref(s), dptr, C.byref(o), _stream_handle(stream)))
+        self._keep = keep  # device inputs must outlive the batch
+        self._nq = int(s.n)
+        return self
+
+    def fetch(self, out: str = "host", cap: Optional[int] = None) -> Hits:
+        n = C.c_int64()
+        L.check(L.lib().tds_fetch_results(self._h, None, 0, L.TDS_MEM_HOST, C.byref(n)))
+        total = int(n.value)
+        m = total if cap is None else min(int(cap), total)
+        if out == "device":
+            import torch
+            buf = torch.empty((max(m, 1), 5), dtype=torch.int64, device="cuda")
+            if m:
+                L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(buf.data_ptr()), m,
+                                                  L.TDS_MEM_DEVICE, C.byref(n)))
+            buf = buf[:m]
+            res = Hits(buf[:, 0], buf[:, 1], buf[:, 2], buf[:, 3].view(torch.float64),
+                       buf[:, 4].view(torch.float64))
+        else:
+            arr = np.empty((max(m, 1), 5), dtype=np.int64)
+            if m:
+                L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(arr.ctypes.data), m,
+                                                  L.TDS_MEM_HOST, C.byref(n)))
+            arr = arr[:m]
+            res = Hits(arr[:, 0].copy(), arr[:, 1].copy(), arr[:, 2].copy(),
+                       arr[:, 3].copy().view(np.float64), arr[:, 4].copy().view(np.float64))
+        self._keep = None
+        return res
+
+    def stats(self) -> dict:
+        s = L.tds_stats()
+        L.check(L.lib().tds_query_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in L.tds_stats._fields_}
+
+    def ranges(self):
+        first = np.empty(max(self._nq, 1), np.int64)
+        last = np.empty(max(self._nq, 1), np.int64)
+        L.check(L.lib().tds_query_ranges(self._h, first.ctypes.data, last.ctypes.data, self._nq))
+        return first[: self._nq], last[: self._nq]
+
+    def close(self):
+        if self._h:
+            L.lib().tds_query_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ flat names
+def build_index(db, num_bins: int, stream=None) -> Index:
+    return Index(db, num_bins, stream=stream)
+
+
+def query_batch(target, q, d, **opts) -> Query:
+    qh = target if isinstance(target, Query) else Query(target)
+    return qh.batch(q, d, **opts)
+
+
+def fetch_results(qh: Query, out: str = "host", cap: Optional[int] = None) -> Hits:
+    return qh.fetch(out=out, cap=cap)
+
+
+def search(index: Index, q, d, **opts) -> Hits:
+    qh = Query(index)
+    try:
+        qh.batch(q, d, **opts)
+        return qh.fetch()
+    finally:
+        qh.close()
+
+
+def plan_bins(t0_sorted, t1_sorted, num_bins: int) -> np.ndarray:
+    """Host-side bin table of entries already sorted by t_start (no GPU)."""
+    t0 = np.ascontiguousarray(t0_sorted, dtype=np.float64)
+    t1 = np.ascontiguousarray(t1_sorted, dtype=np.float64)
+    n = C.c_int64()
+    L.check(L.lib().tds_plan_bins(t0.ctypes.data, t1.ctypes.data, t0.size, int(num_bins), None, 0,
+                                  C.byref(n)))
+    out = (L.tds_bin * max(n.value, 1))()
+    L.check(L.lib().tds_plan_bins(t0.ctypes.data, t1.ctypes.data, t0.size, int(num_bins), out,
+                                  n.value, C.byref(n)))
+    return _bins_array(out, n.value)
+
+
+def plan_ranges(bins: np.ndarray, t0, t1):
+    """Host-side candidate range per (t0, t1) span from a bin table."""
+    b = np.ascontiguousarray(bins, dtype=BIN_DTYPE)
+    t0 = np.ascontiguousarray(t0, dtype=np.float64)
+    t1 = np.ascontiguousarray(t1, dtype=np.float64)
+    first = np.empty(max(t0.size, 1), np.int64)
+    last = np.empty(max(t0.size, 1), np.int64)
+    L.check(L.lib().tds_plan_ranges(b.ctypes.data_as(C.POINTER(L.tds_bin)), b.size, t0.ctypes.data,
+                                    t1.ctypes.data, t0.size, first.ctypes.data, last.ctypes.data))
+    return first[: t0.size], last[: t0.size]

@@ -1,0 +1,130 @@
+"""C ABI: symbols, and the host-side index logic pinned to the paper's Figs. 1-2.
+
+CPU only: nothing here launches a kernel.
+"""
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_1405_7461_amd as tds
+from paper_1405_7461_amd import _lib as L
+from golden_io import fig1, fig2
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "tds.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tds_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, f"{name} not bound in _lib.SIGNATURES"
+
+
+def test_abi_version():
+    assert L.lib().tds_abi_version() == 1
+
+
+def test_struct_sizes_match_header():
+    # tds_hit is five 8-byte fields; tds_bin five; tds_segments 16 + 9 pointers
+    import ctypes as C
+    assert C.sizeof(L.tds_hit) == 40
+    assert C.sizeof(L.tds_bin) == 40
+    assert C.sizeof(L.tds_segments) == 16 + 9 * 8
+    assert C.sizeof(L.tds_query_opts) == 6 * 4 + 8 + 2 * 4
+
+
+def test_fig1_bin_table():
+    t0, t1, bins, _ = fig1()
+    got = tds.plan_bins(t0, t1, 4)
+    assert len(got) == 4
+    for g, (j, start, end, first, last) in zip(got, bins):
+        assert (g["bin"], g["start"], g["end"], g["first"], g["last"]) == (j, start, end, first, last)
+    # bin counts 6/3/3/3
+    assert list(got["last"] - got["first"] + 1) == [6, 3, 3, 3]
+
+
+def test_lookup_example():
+    t0, t1, _, lk = fig1()
+    bins = tds.plan_bins(t0, t1, 4)
+    f, l = tds.plan_ranges(bins, [lk["t0"]], [lk["t1"]])
+    assert (f[0], l[0]) == (lk["first"], lk["last"])
+    cand = np.arange(f[0], l[0] + 1)
+    ovl = cand[(t0[cand] < lk["t1"]) & (t1[cand] > lk["t0"])]
+    assert list(ovl) == lk["overlap"]
+
+
+def test_fig2_interaction_totals():
+    t0, t1, _, _ = fig1()
+    bins = tds.plan_bins(t0, t1, 4)
+    batches, totals = fig2()
+    for s, (want, printed) in totals.items():
+        k = s // 10
+        total = 0
+        for g in range(0, len(batches), k):
+            grp = batches[g:g + k]
+            a = min(b[1] for b in grp)
+            b_ = max(b[2] for b in grp)
+            f, l = tds.plan_ranges(bins, [a], [b_])
+            total += sum(b[0] for b in grp) * (l[0] - f[0] + 1)
+        assert total == want, (s, total)
+    # only the single-batch total is reading-independent
+    assert totals[60][0] == totals[60][1]
+
+
+def test_ranges_superset_of_overlaps():
+    rng = np.random.default_rng(7)
+    n = 3000
+    t0 = np.sort(rng.uniform(0, 50, n))
+    t1 = t0 + rng.exponential(2.0, n) + 1e-3
+    qa = rng.uniform(-5, 55, 400)
+    qb = qa + rng.exponential(1.0, 400) + 1e-3
+    for m in (1, 7, 100, 5000):
+        bins = tds.plan_bins(t0, t1, m)
+        assert bins["last"][-1] == n - 1 and bins["first"][0] == 0
+        f, l = tds.plan_ranges(bins, qa, qb)
+        for i in range(qa.size):
+            ov = np.nonzero((t0 < qb[i]) & (t1 > qa[i]))[0]
+            if ov.size:
+                assert f[i] <= ov.min() and ov.max() <= l[i]
+        if m == 1:
+            nonempty = l >= f
+            assert np.all(f[nonempty] == 0) and np.all(l[nonempty] == n - 1)
+
+
+def test_plan_bins_rejects_bad_input():
+    with pytest.raises(tds.TdsError):
+        tds.plan_bins([0.0, 2.0, 1.0], [1.0, 3.0, 2.0], 2)  # not sorted
+    with pytest.raises(tds.TdsError):
+        tds.plan_bins([0.0, 1.0], [1.0, 1.0], 2)  # empty span
+    with pytest.raises(tds.TdsError):
+        tds.plan_bins([0.0], [1.0], 0)
+    with pytest.raises(tds.TdsError):
+        tds.plan_bins([np.nan], [1.0], 3)
+
+
+def test_build_index_validates_before_the_device():
+    from gen import fixtures as fx
+    db, _ = fx.random_small()
+    bad = db.subset(np.arange(len(db)))
+    bad.t1[5] = bad.t0[5] - 1.0
+    with pytest.raises(tds.TdsError) as e:
+        tds.build_index(bad, 10)
+    assert e.value.code == L.TDS_EINVAL
+    with pytest.raises(tds.TdsError) as e:
+        tds.build_index(db, 0)
+    assert e.value.code == L.TDS_EINVAL
+    bad2 = db.subset(np.arange(len(db)))
+    bad2.y1[2] = np.inf
+    with pytest.raises(tds.TdsError) as e:
+        tds.build_index(bad2, 10)
+    assert e.value.code == L.TDS_EINVAL

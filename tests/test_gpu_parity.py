@@ -1,0 +1,244 @@
+"""HIP path against the oracle, element by element (GPU).
+
+Every case compares the sorted (query, entry) hit set exactly and the
+interval ends to 1e-9 relative (they are expected to be bitwise equal, as
+both sides evaluate the same binary64 expression).
+"""
+import numpy as np
+import pytest
+
+import gen
+from gen import fixtures as fx
+import oracle
+import paper_1405_7461_amd as tds
+from paper_1405_7461_amd import _lib as L
+from golden_io import fig1
+from gpu_util import compare, run, say
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp64", "fp32_refine"]
+
+
+def test_fig1_index_on_device():
+    t0, t1, bins, lk = fig1()
+    db = fx.time_only(t0, t1)
+    ix = tds.build_index(db, 4)
+    got = ix.bins()
+    assert [tuple(r) for r in got[["bin", "start", "end", "first", "last"]]] == \
+        [(j, s, e, f, l) for j, s, e, f, l in bins]
+    info = ix.info()
+    assert info["n"] == 15 and info["nonempty_bins"] == 4 and info["bin_width"] == 3.0
+    q = fx.segments_from_rows([[0, 0, 0, lk["t0"], 0, 0, 0, lk["t1"]]]).with_d(1e9)
+    h, st, (f, l) = run(db, q, 4, index=ix)
+    assert (f[0], l[0]) == (lk["first"], lk["last"])
+    # with a huge d every overlapping entry is a hit
+    assert sorted(h.entry.tolist()) == lk["overlap"]
+    assert st["n_overlap"] == len(lk["overlap"])
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("tiling", ["periodic", "range"])
+def test_c1_full(mode, tiling):
+    db, q, m = gen.make_config("C1")
+    say(f"C1 {mode} {tiling}: db {len(db)} q {len(q)}")
+    want = oracle.search(db, q)
+    got, st, _ = run(db, q, m, mode=mode, tiling=tiling, count_overlap=True)
+    bit = compare(got, want, db, "C1")
+    assert bit
+    assert st["n_overlap"] == want.n_overlap
+    if mode == "fp64":
+        assert st["n_overlap_k"] == want.n_overlap
+    else:
+        assert st["n_overlap_k"] >= want.n_overlap
+        assert st["n_refine"] >= st["n_hit"]
+    assert st["n_eval"] >= st["n_overlap"]
+
+
+def _fixture_cases():
+    db, q = fx.random_small()
+    yield "random_small", db, q, 3
+    db, q = fx.random_small(n_e=700, n_q=300, box=6.0, seed=12, d=0.9)
+    yield "random_mid", db, q, 17
+    db, q = fx.dense_box()
+    yield "dense_box", db, q, 9
+    db, q = fx.all_hit()
+    yield "all_hit", db, q, 5
+    db, q, _ = fx.near_threshold()
+    yield "near_threshold", db, q, 4
+    db, q, params = fx.passing_pairs()
+    yield "passing", db, q.with_d(np.array([p["d"] for p in params])), 8
+    db, q, _ = fx.stationary_pairs()
+    yield "stationary", db, q, 1
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_fixtures(mode):
+    for name, db, q, m in _fixture_cases():
+        say(f"fixture {name} {mode}")
+        want = oracle.search(db, q)
+        for tiling in ("periodic", "range"):
+            got, st, _ = run(db, q, m, mode=mode, tiling=tiling)
+            compare(got, want, db, f"{name}/{tiling}")
+        if name == "all_hit":
+            assert len(want) == want.n_overlap
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_launch_shape_invariance(mode):
+    db, q = fx.dense_box(ntraj=300, L=40, box=8.0, nq=30, seed=31, d=1.1)
+    want = oracle.search(db, q)
+    assert len(want) > 200
+    for m in (1, 7, 40, 1000):
+        ix = tds.build_index(db, m)
+        for block in (64, 256, 1024):
+            for bs in (1, 7, 128, 1000):
+                for tiling in ("periodic", "range"):
+                    say(f"invariance {mode} m={m} block={block} bs={bs} {tiling}")
+                    got, st, _ = run(db, q, m, index=ix, mode=mode, block_size=block,
+                                     batch_size=bs, tiling=tiling)
+                    compare(got, want, db, f"m={m} block={block} bs={bs} {tiling}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_c2_reduced(mode):
+    db = gen.make_db("C2", ntraj=300)
+    qb = gen.make_queries("C2", nq=20)
+    q = gen.concat([qb.with_d(d) for d in (1.0, 5.0, 25.0)])
+    say(f"C2 reduced {mode}: db {len(db)} q {len(q)}")
+    want = oracle.search(db, q)
+    assert len(want) > 100
+    for tiling, bs in (("periodic", 100), ("range", 512)):
+        got, st, _ = run(db, q, 1000, mode=mode, tiling=tiling, batch_size=bs)
+        compare(got, want, db, f"C2r/{tiling}")
+        assert st["n_overlap"] == want.n_overlap
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_c3_reduced(mode):
+    db = gen.make_db("C3", ntraj=2000, L=40)
+    qb = gen.make_queries("C3", nq=30, L=40)
+    q = gen.concat([qb.with_d(d) for d in (0.001, 0.01, 0.05)])
+    say(f"C3 reduced {mode}: db {len(db)} q {len(q)}")
+    want = oracle.search(db, q)
+    assert len(want) > 10
+    got, st, _ = run(db, q, 40, mode=mode, tiling="range", batch_size=256)
+    compare(got, want, db, "C3r")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_c4_reduced(mode):
+    db = gen.make_db("C4", ntraj=300)
+    q = gen.make_queries("C4", nq=24)
+    say(f"C4 reduced {mode}: db {len(db)} q {len(q)}")
+    want = oracle.search(db, q)
+    got, st, _ = run(db, q, 1000, mode=mode, tiling="range", batch_size=256)
+    compare(got, want, db, "C4r")
+    got, st, _ = run(db, q, 400, mode=mode, tiling="periodic", batch_size=64)
+    compare(got, want, db, "C4r/periodic")
+
+
+def test_c5_requests_reduced():
+    db = gen.make_db("C5", ntraj=500)
+    ix = tds.build_index(db, 800)
+    for r in range(4):
+        q = gen.make_queries("C5", request=r)
+        say(f"C5 request {r}: {len(q)} segments, d={q.d[0]:.3f}")
+        want = oracle.search(db, q)
+        for mode in MODES:
+            got, st, _ = run(db, q, 800, index=ix, mode=mode, tiling="range", batch_size=128)
+            compare(got, want, db, f"C5 req {r} {mode}")
+
+
+def test_overflow_retry():
+    db, q = fx.dense_box(ntraj=200, L=30, box=4.0, nq=20, seed=41, d=1.5)
+    want = oracle.search(db, q)
+    assert len(want) > 1000
+    for mode in MODES:
+        got, st, _ = run(db, q, 30, mode=mode, capacity=1, max_retries=2)
+        compare(got, want, db, f"retry {mode}")
+        assert st["retries"] == 1
+    with pytest.raises(tds.TdsError) as e:
+        run(db, q, 30, capacity=1, max_retries=0)
+    assert e.value.code == L.TDS_EOVERFLOW
+
+
+def test_empty_inputs():
+    db, q = fx.random_small()
+    ix = tds.build_index(db, 8)
+    got, st, _ = run(db, q.subset(np.arange(0)), 8, index=ix)
+    assert len(got) == 0 and st["n_eval"] == 0
+    ix0 = tds.build_index(db.subset(np.arange(0)), 8)
+    got, st, _ = run(None, q, 8, index=ix0)
+    assert len(got) == 0
+    assert ix0.info()["n"] == 0
+    # query entirely outside the database's time extent
+    far = q.subset(np.arange(len(q)))
+    far.t0 += 1e6
+    far.t1 += 1e6
+    got, st, _ = run(db, far, 8, index=ix)
+    assert len(got) == 0 and st["n_eval"] == 0
+
+
+def test_device_inputs_and_outputs():
+    import torch
+    db, q = fx.dense_box(ntraj=100, L=20, nq=10, seed=51)
+    want = oracle.search(db, q)
+
+    class Dev:
+        pass
+
+    dq = Dev()
+    for f in gen.workloads.FIELDS:
+        setattr(dq, f, torch.as_tensor(getattr(q, f), device="cuda"))
+    ddb = Dev()
+    for f in gen.workloads.FIELDS:
+        setattr(ddb, f, torch.as_tensor(getattr(db, f), device="cuda"))
+    ddb.traj = torch.as_tensor(db.traj, device="cuda")
+    ix = tds.build_index(ddb, 20)
+    qh = tds.Query(ix)
+    qh.batch(dq, torch.as_tensor(q.d, device="cuda"), mode="fp32_refine", tiling="range")
+    h = qh.fetch(out="device")
+    assert h.query.is_cuda
+    compare(h.sorted(), want, db, "device io")
+    qh.close()
+
+
+def test_invalid_device_query_reported_at_fetch():
+    import torch
+    db, q = fx.random_small()
+    ix = tds.build_index(db, 4)
+
+    class Dev:
+        pass
+
+    dq = Dev()
+    for f in gen.workloads.FIELDS:
+        setattr(dq, f, torch.as_tensor(getattr(q, f), device="cuda"))
+    dq.t1[3] = dq.t0[3]
+    qh = tds.Query(ix)
+    qh.batch(dq, torch.as_tensor(q.d, device="cuda"))
+    with pytest.raises(tds.TdsError) as e:
+        qh.fetch()
+    assert e.value.code == L.TDS_EINVAL
+    # the handle is usable again afterwards
+    dq.t1[3] = dq.t0[3] + 0.5
+    q2 = q.subset(np.arange(len(q)))
+    q2.t1[3] = q2.t0[3] + 0.5
+    qh.batch(dq, torch.as_tensor(q.d, device="cuda"))
+    compare(qh.fetch().sorted(), oracle.search(db, q2), db, "after error")
+    qh.close()
+
+
+def test_host_query_validation():
+    db, q = fx.random_small()
+    ix = tds.build_index(db, 4)
+    bad = q.subset(np.arange(len(q)))
+    bad.x0[1] = np.nan
+    with pytest.raises(tds.TdsError) as e:
+        run(db, bad, 4, index=ix)
+    assert e.value.code == L.TDS_EINVAL
+    with pytest.raises(tds.TdsError):
+        run(db, q.with_d(-1.0), 4, index=ix)
+    with pytest.raises(tds.TdsError):
+        run(db, q, 4, index=ix, block_size=96)
