@@ -42,7 +42,7 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 FP64_PEAK = 78.6e12
 # Algorithmic work per temporally overlapping pair:
 FP64_FLOPS_PER_PAIR = 49          # binary64 decision, FMA = 2
-FILTER_OPS_PER_PAIR = 8           # binary32 box test: 2 time + 6 space compares
+FILTER_OPS_PER_PAIR = 6           # binary32 box test: 6 bound compares
 
 
 def log(*a):
@@ -82,6 +82,10 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
     import paper_1405_7461_amd as tds
     qh = tds.Query(ix)
     stream = torch.cuda.current_stream()
+    # one untimed pass that also counts overlapping pairs (checked against N_ovl)
+    qh.batch(dq, dq.d, count_overlap=True, stream=stream, **opts)
+    qh.fetch(out="device")
+    counted = qh.stats()["n_overlap"]
     lat, pair_ms, stats = [], [], None
     for i in range(warmup + steps):
         torch.cuda.synchronize()
@@ -101,9 +105,10 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
     ms = float(lat.mean() * 1e3)
     return dict(ms_per_step=ms, value=n_ovl / (ms / 1e3), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pair_ms=float(np.mean(pair_ms)),
-                n_hit=int(n_hit), n_eval=int(stats["n_eval"]), n_overlap=int(stats["n_overlap"]),
+                n_hit=int(n_hit), n_eval=int(stats["n_eval"]), n_overlap=int(counted),
                 n_refine=int(stats["n_refine"]), retries=int(stats["retries"]),
-                n_items=int(stats["n_items"]), grid=int(stats["grid"]), opts=opts)
+                n_items=int(stats["n_items"]), grid=int(stats["grid"]), prep_ms=float(stats["ms_prep"]),
+                opts=opts)
 
 
 def cpu_baseline(db, q, n_ovl_total, target_s=10.0):
@@ -128,6 +133,81 @@ def cpu_baseline(db, q, n_ovl_total, target_s=10.0):
                 seconds=dt)
 
 
+def batching_form(log_fn=log, reps=10):
+    """C4: uneven query set, per-query d, one persistent launch, autotuned."""
+    import torch
+    import gen
+    import paper_1405_7461_amd as tds
+    from paper_1405_7461_amd.autotune import tune
+    db = gen.make_db("C4")
+    q = gen.make_queries("C4")
+    n_ovl = overlap_count(db, q)
+    dq = to_device(q)
+    t0 = time.perf_counter()
+    res = tune(db, dq, dq.d, mode="fp32_refine", num_bins=(400, 1000, 2000),
+               tilings=("range",), blocks=(256, 1024), reps=2, use_cache=False,
+               cache=None)
+    tune_s = time.perf_counter() - t0
+    ix = tds.build_index(db, res.num_bins)
+    r = run_form(ix, dq, res.opts, reps, 2, n_ovl)
+    ix.close()
+    out = dict(workload="C4: 1M-segment exponential-step walk (2,500 x 400); 256 query trajectories of "
+                        "log-uniform length 10-2000 (segments of 1/8), per-trajectory d in {1,5,25}",
+               n_query_segments=len(q), n_overlap=n_ovl, tuned=dict(num_bins=res.num_bins, **res.opts),
+               tune_s=round(tune_s, 2), trials=len(res.trials), value=r["value"], unit="pair-tests/s",
+               ms_per_step=r["ms_per_step"], pair_ms=r["pair_ms"], n_hit=r["n_hit"], n_eval=r["n_eval"])
+    log_fn(f"batching (C4): {out['value']:.4g} pair-tests/s, {out['ms_per_step']:.3f} ms/step, tuned {out['tuned']}")
+    return out
+
+
+def serving_form(log_fn=log, n_requests=400, rates=(0.5, 0.8, 0.95)):
+    """C5: 10M-segment resident index, Poisson request arrivals at 3 rates."""
+    import gen
+    import paper_1405_7461_amd as tds
+    from paper_1405_7461_amd.serving import Request, Server, poisson_arrivals
+    t0 = time.perf_counter()
+    db = gen.make_db("C5")
+    ix = tds.build_index(db, gen.CONFIGS["C5"]["bins"])
+    t1s = np.sort(db.t1)
+    t0s = np.sort(db.t0)
+    build_s = time.perf_counter() - t0
+
+    def make(n, arrivals):
+        reqs = []
+        for i in range(n):
+            q = gen.make_queries("C5", request=i)
+            r = Request(rid=i, seg=q, d=q.d.copy(), arrival=float(arrivals[i]))
+            r.n_overlap = int((np.searchsorted(t0s, q.t1, side="left") - np.searchsorted(t1s, q.t0, side="right")).sum())
+            reqs.append(r)
+        return reqs
+
+    opts = dict(mode="fp32_refine", tiling="range")
+    # saturation: every request waiting at t = 0
+    reqs = make(n_requests, np.zeros(n_requests))
+    srv = Server(ix, pool_bytes=256e6, streams=2, opts=opts)
+    sat = srv.run(reqs)
+    srv.close()
+    sat_rate = n_requests / sat["wall_s"]
+    sat_pairs = sum(r.n_overlap for r in reqs) / sat["wall_s"]
+    runs = []
+    for k, f in enumerate(rates):
+        arr = poisson_arrivals(n_requests, f * sat_rate, seed=14057461 + 500 + k)
+        reqs = make(n_requests, arr)
+        srv = Server(ix, pool_bytes=256e6, streams=2, opts=opts)
+        st = srv.run(reqs)
+        srv.close()
+        runs.append(dict(rate_frac=f, rate_req_s=f * sat_rate, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                         pair_tests_s=sum(r.n_overlap for r in reqs) / st["wall_s"],
+                         mean_batch_requests=st["mean_batch_requests"], batches=st["n_batches"]))
+        log_fn(f"serving at {f:.2f} x saturation ({f * sat_rate:.0f} req/s): p50 {st['p50_ms']:.3f} ms, "
+               f"p99 {st['p99_ms']:.3f} ms, {runs[-1]['pair_tests_s']:.4g} pair-tests/s")
+    ix.close()
+    return dict(workload="C5: 10M-segment Gaussian walk (25,000 x 400) resident; requests of log-uniform "
+                         "length 10-5000 (segments of 1/16), d log-uniform in [0.5, 50]; Poisson arrivals",
+                n_requests=n_requests, build_s=round(build_s, 2), saturation_req_s=sat_rate,
+                saturation_pair_tests_s=sat_pairs, saturation_p50_ms=sat["p50_ms"], rates=runs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +215,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32_refine,fp64")
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search is not "
@@ -158,8 +240,8 @@ def main():
     torch.cuda.synchronize()
 
     forms = {
-        "fp32_refine": dict(mode="fp32_refine", tiling="range", batch_size=512, block_size=256),
-        "fp64": dict(mode="fp64", tiling="range", batch_size=512, block_size=256),
+        "fp32_refine": dict(mode="fp32_refine", tiling="range", block_size=256),
+        "fp64": dict(mode="fp64", tiling="range", block_size=256),
     }
     results = {}
     for name in args.forms.split(","):
@@ -205,6 +287,10 @@ def main():
         "roofline": roof,
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "opts"} for k, v in results.items()},
     }
+    if not args.no_batching:
+        line["batching"] = batching_form()
+    if not args.no_serving:
+        line["serving"] = serving_form()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(db, q, n_ovl)
     print(json.dumps(line), flush=True)

@@ -90,18 +90,19 @@ typedef struct {
 #define TDS_TILE_RANGE 1        /* runs of <= batch_size segments with the same candidate bin range */
 
 /* Query flags. */
-#define TDS_QF_TIMING 1         /* record per-stage HIP event times (tds_stats.ms_*) */
-#define TDS_QF_COUNT_OVERLAP 2  /* the pair kernel also counts overlapping pairs it examined */
+#define TDS_QF_TIMING 1          /* record per-stage HIP event times (tds_stats.ms_*) */
+#define TDS_QF_COUNT_OVERLAP 2   /* count pairs whose spans overlap (tds_stats.n_overlap) */
+#define TDS_QF_KERNEL_OVERLAP 4  /* the pair kernel also counts the overlapping pairs it examined */
 
 typedef struct {
     int32_t mode;        /* TDS_MODE_* */
     int32_t tiling;      /* TDS_TILE_* */
-    int32_t batch_size;  /* query segments per tile, 1..4096; 0 = 128 */
+    int32_t batch_size;  /* TDS_TILE_PERIODIC: query segments per tile (s), 1..65536; 0 = 128 */
     int32_t block_size;  /* pair-kernel threads per workgroup: 64, 128, 256, 512 or 1024; 0 = 256 */
-    int32_t reserved0;   /* 0 (a work item is block_size x entries-per-lane candidates) */
+    int32_t reserved0;   /* 0 */
     int32_t max_retries; /* result-buffer regrowths allowed; < 0 = 4 */
     int64_t capacity;    /* initial result capacity (hits); 0 = library default */
-    int32_t grid;        /* pair-kernel workgroups; 0 = library default */
+    int32_t grid;        /* pair-kernel workgroups; 0 = as many as are resident at once */
     int32_t flags;       /* TDS_QF_* */
 } tds_query_opts;
 
@@ -118,18 +119,20 @@ typedef struct {
 typedef struct {
     int64_t n_query;     /* query segments in the last batch */
     int64_t n_eval;      /* candidate pairs examined: sum over tiles of segments x range */
-    int64_t n_overlap;   /* pairs with a common span of positive length (from the time arrays) */
-    int64_t n_overlap_k; /* the same, counted in the pair kernel (TDS_QF_COUNT_OVERLAP), else -1 */
-    int64_t n_refine;    /* FP32_REFINE: pairs passed to the binary64 decision; FP64: -1 */
+    int64_t n_overlap;   /* pairs with a common span of positive length, counted from the sorted
+                            time arrays (TDS_QF_COUNT_OVERLAP), else -1 */
+    int64_t n_overlap_k; /* the same, counted in the pair kernel (TDS_QF_KERNEL_OVERLAP), else -1 */
+    int64_t n_refine;    /* pairs the pair kernel passed to the refine kernel: FP32_REFINE the
+                            filter's survivors, FP64 the decided hits */
     int64_t n_hit;
-    int64_t n_tiles;
-    int64_t n_items;
+    int64_t n_tiles;     /* tiles (groups of query segments sharing one candidate range) */
+    int64_t n_items;     /* work units of the pair kernel (query segment x entry chunk) */
     int32_t retries;
     int32_t grid;        /* pair-kernel workgroups used */
     float ms_prep;       /* TDS_QF_TIMING: query preparation, sort and tiling */
     float ms_pair;       /* pair kernel (last launch) */
     float ms_fetch;      /* result translation + copy */
-    float reserved;
+    float ms_refine;     /* refine kernel (last launch) */
 } tds_stats;
 
 typedef struct {

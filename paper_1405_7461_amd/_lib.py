@@ -27,6 +27,7 @@ TDS_TILE_PERIODIC = 0
 TDS_TILE_RANGE = 1
 TDS_QF_TIMING = 1
 TDS_QF_COUNT_OVERLAP = 2
+TDS_QF_KERNEL_OVERLAP = 4
 
 _P = C.c_void_p
 
@@ -58,7 +59,7 @@ class tds_stats(C.Structure):
                 ("n_overlap_k", C.c_int64), ("n_refine", C.c_int64), ("n_hit", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_items", C.c_int64), ("retries", C.c_int32),
                 ("grid", C.c_int32), ("ms_prep", C.c_float), ("ms_pair", C.c_float),
-                ("ms_fetch", C.c_float), ("reserved", C.c_float)]
+                ("ms_fetch", C.c_float), ("ms_refine", C.c_float)]
 
 
 class tds_index_info(C.Structure):

@@ -154,7 +154,8 @@ class Query:
         self._nq = 0
 
     def batch(self, q, d, mode="fp64", tiling="periodic", batch_size=0, block_size=0,
-              capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False, stream=None):
+              capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False,
+              kernel_overlap=False, stream=None):
         s, keep, mem = _segments(q, with_traj=False)
         if mem == L.TDS_MEM_DEVICE:
             import torch
@@ -168,7 +169,8 @@ class Query:
             dd = np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.float64), (s.n,)))
             dptr = dd.ctypes.data
         keep.append(dd)
-        flags = (L.TDS_QF_TIMING if timing else 0) | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
+        flags = ((L.TDS_QF_TIMING if timing else 0) | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
+                 | (L.TDS_QF_KERNEL_OVERLAP if kernel_overlap else 0))
         o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,
                              int(max_retries), int(capacity), int(grid), flags)
         L.check(L.lib().tds_query_batch(self._h, C.byref(s), dptr, C.byref(o), _stream_handle(stream)))

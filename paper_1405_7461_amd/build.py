@@ -26,24 +26,27 @@ COMMON = [
 SOURCES = ["tds_kernels.hip", "tds_api.cpp"]
 
 
-def build(verbose: bool = False, extra: list[str] | None = None) -> Path:
-    BUILD.mkdir(exist_ok=True)
+def build(verbose: bool = False, extra: list[str] | None = None, out: Path | None = None) -> Path:
+    """Compile libtds.so (or `out`, with `extra` compiler flags)."""
+    lib = LIB if out is None else Path(out)
+    bdir = BUILD if out is None else lib.parent / (lib.stem + "_build")
+    bdir.mkdir(parents=True, exist_ok=True)
     objs = []
     for src in SOURCES:
-        obj = BUILD / (Path(src).stem + ".o")
+        obj = bdir / (Path(src).stem + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         cmd = [HIPCC, *COMMON, *(extra or []), *lang, "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
+    tmp = lib.with_suffix(f".so.tmp{os.getpid()}")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -44,7 +44,7 @@ struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
     hipError_t ensure(size_t need) {
-        if (need <= bytes) return hipSuccess;
+        if (need <= bytes && p) return hipSuccess;
         if (p) {
             hipError_t e = hipFree(p);
             if (e != hipSuccess) return e;
@@ -78,7 +78,8 @@ void plan_bins(const double *t0, const double *t1, int64_t n, int32_t m, std::ve
                double *t_first, double *t_last, double *width) {
     out->clear();
     if (n == 0) {
-        *t_first = *t_last = *width = 0.0;
+        *t_first = *t_last = 0.0;
+        *width = 1.0;
         return;
     }
     double tf = t0[0];
@@ -115,9 +116,9 @@ struct tds_index {
     int device = 0;
     int64_t n = 0;
     int32_t m = 0;
-    double t_first = 0, t_last = 0, width = 0;
+    double t_first = 0, t_last = 0, width = 1;
     std::vector<tds_bin> bins;
-    DBuf t0, t1, x0, y0, z0, vx, vy, vz, boxa, boxb, orig, traj, t1s;
+    DBuf t0, t1, x0, y0, z0, vx, vy, vz, boxxy, boxz, orig, traj, t1s;
     DBuf bstart, bpend, bfirst, blast;
     DevIndex dev{};
     int64_t device_bytes = 0;
@@ -126,12 +127,12 @@ struct tds_index {
 
 struct tds_query {
     tds_index *ix = nullptr;
-    int32_t cap_q = 0;  // query slots allocated
-    DBuf rec, box, rec_s, box_s, first, last, first_s, last_s, key_in, key_out, val_in, perm;
-    DBuf head, tile_of_head, tiles, items, item_off, ctr, sort_tmp, scan_tmp;
-    DBuf qstage, hits, out_stage;
-    size_t sort_bytes = 0, scan_bytes = 0;
-    unsigned long long cap_hits = 0;
+    int32_t cap_q = 0;        // query slots allocated
+    int32_t cap_buckets = 0;  // bucket slots allocated
+    DBuf rec, box, rec_s, box_s, first, last, first_s, last_s, key, perm;
+    DBuf bcount, bj2, bcursor, bq_off, tiles, units, unit_off, ctr;
+    DBuf qstage, cand, hits, out_stage;
+    unsigned long long cap_cand = 0, cap_hits = 0;
     Counters *host_ctr = nullptr;  // pinned
     hipStream_t stream = nullptr;
     DevBatch b{};
@@ -139,7 +140,7 @@ struct tds_query {
     int block = 256, grid = 0;
     bool pending = false, fetched = false;
     tds_stats stats{};
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 extern "C" {
@@ -198,7 +199,8 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     *out = nullptr;
     if (db->n < 0 || db->n >= (int64_t)INT32_MAX)
         return fail(TDS_EINVAL, "tds_build_index: n = %lld out of range", (long long)db->n);
-    if (opts->num_bins < 1) return fail(TDS_EINVAL, "tds_build_index: num_bins must be >= 1");
+    if (opts->num_bins < 1 || opts->num_bins > (1 << 24))
+        return fail(TDS_EINVAL, "tds_build_index: num_bins must be in 1..2^24");
     if (db->mem != TDS_MEM_HOST && db->mem != TDS_MEM_DEVICE)
         return fail(TDS_EINVAL, "tds_build_index: bad mem");
     const int64_t n = db->n;
@@ -210,7 +212,6 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
 
     // Host copies (the sort and the bin table are built on the host once).
     std::vector<double> host[8];
-    std::vector<int64_t> traj_h;
     const double *h[8];
     for (int k = 0; k < 8; ++k) {
         if (db->mem == TDS_MEM_DEVICE && n > 0) {
@@ -220,12 +221,6 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
         } else {
             h[k] = src[k];
         }
-    }
-    const int64_t *traj_src = db->traj_id;
-    if (traj_src && db->mem == TDS_MEM_DEVICE && n > 0) {
-        traj_h.resize(n);
-        HIP_TRY(hipMemcpy(traj_h.data(), traj_src, n * sizeof(int64_t), hipMemcpyDeviceToHost));
-        traj_src = traj_h.data();
     }
     for (int64_t i = 0; i < n; ++i)
         if (!seg_ok(h, i))
@@ -269,18 +264,18 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
                                 #expr, hipGetErrorString(e_)));                            \
     } while (0)
 
-    size_t d8 = (size_t)std::max<int64_t>(n, 1) * 8;
+    const size_t n1 = (size_t)std::max<int64_t>(n, 1);
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
                     &ix->traj, &ix->t1s})
-        IX_TRY(b->ensure(d8));
-    IX_TRY(ix->boxa.ensure((size_t)std::max<int64_t>(n, 1) * 16));
-    IX_TRY(ix->boxb.ensure((size_t)std::max<int64_t>(n, 1) * 16));
-    IX_TRY(ix->orig.ensure((size_t)std::max<int64_t>(n, 1) * 4));
-    size_t b8 = (size_t)std::max<int64_t>(nb, 1) * 8, b4 = (size_t)std::max<int64_t>(nb, 1) * 4;
-    IX_TRY(ix->bstart.ensure(b8));
-    IX_TRY(ix->bpend.ensure(b8));
-    IX_TRY(ix->bfirst.ensure(b4));
-    IX_TRY(ix->blast.ensure(b4));
+        IX_TRY(b->ensure(n1 * 8));
+    IX_TRY(ix->boxxy.ensure(n1 * 16));
+    IX_TRY(ix->boxz.ensure(n1 * 8));
+    IX_TRY(ix->orig.ensure(n1 * 4));
+    const size_t nb1 = (size_t)std::max<int64_t>(nb, 1);
+    IX_TRY(ix->bstart.ensure(nb1 * 8));
+    IX_TRY(ix->bpend.ensure(nb1 * 8));
+    IX_TRY(ix->bfirst.ensure(nb1 * 4));
+    IX_TRY(ix->blast.ensure(nb1 * 4));
 
     std::vector<double> bs(nb), bp(nb);
     std::vector<int32_t> bf(nb), bl(nb);
@@ -315,10 +310,10 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
                                   st));
             traj_dev = dtraj.as<int64_t>();
         }
-        IX_TRY(launch_ingest(rawp, n, dperm.as<int32_t>(), traj_dev, DevIndex{}, ix->t0.as<double>(),
+        IX_TRY(launch_ingest(rawp, n, dperm.as<int32_t>(), traj_dev, ix->t0.as<double>(),
                              ix->t1.as<double>(), ix->x0.as<double>(), ix->y0.as<double>(),
                              ix->z0.as<double>(), ix->vx.as<double>(), ix->vy.as<double>(),
-                             ix->vz.as<double>(), ix->boxa.as<float4>(), ix->boxb.as<float4>(),
+                             ix->vz.as<double>(), ix->boxxy.as<float4>(), ix->boxz.as<float2>(),
                              ix->orig.as<int32_t>(), ix->traj.as<int64_t>(), st));
         IX_TRY(hipMemcpyAsync(ix->t1s.p, t1s.data(), n * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->bstart.p, bs.data(), nb * 8, hipMemcpyHostToDevice, st));
@@ -335,6 +330,9 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     DevIndex &d = ix->dev;
     d.n = n;
     d.nb = (int32_t)nb;
+    d.m = ix->m;
+    d.t_first = ix->t_first;
+    d.width = ix->width > 0.0 ? ix->width : 1.0;
     d.t0 = ix->t0.as<double>();
     d.t1 = ix->t1.as<double>();
     d.x0 = ix->x0.as<double>();
@@ -343,11 +341,10 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.vx = ix->vx.as<double>();
     d.vy = ix->vy.as<double>();
     d.vz = ix->vz.as<double>();
-    d.boxa = ix->boxa.as<float4>();
-    d.boxb = ix->boxb.as<float4>();
+    d.boxxy = ix->boxxy.as<float4>();
+    d.boxz = ix->boxz.as<float2>();
     d.orig = ix->orig.as<int32_t>();
     d.traj = ix->traj.as<int64_t>();
-    d.t0s = d.t0;  // entries are sorted by t_start
     d.t1s = ix->t1s.as<double>();
     d.bstart = ix->bstart.as<double>();
     d.bpend = ix->bpend.as<double>();
@@ -361,7 +358,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.band_abs = std::ldexp(1.0, -40);
     d.ext_max = ext_max;
     d.mag_max = mag_max;
-    ix->device_bytes = (int64_t)(n * (8 * 8 + 32 + 4 + 8 + 8) + nb * 24);
+    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 8 + 4 + 8 + 8) + nb * 24);
     *out = ix;
     return TDS_OK;
 }
@@ -373,7 +370,7 @@ int tds_index_info_get(const tds_index *ix, tds_index_info *out) {
     out->nonempty_bins = (int32_t)ix->bins.size();
     out->t_first = ix->t_first;
     out->t_last = ix->t_last;
-    out->bin_width = ix->width;
+    out->bin_width = ix->n > 0 ? ix->width : 0.0;
     out->device_bytes = ix->device_bytes;
     return TDS_OK;
 }
@@ -388,7 +385,7 @@ int tds_index_bins(const tds_index *ix, tds_bin *out, int64_t cap, int64_t *n_ou
 void tds_index_destroy(tds_index *ix) {
     if (!ix) return;
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
-                    &ix->boxa, &ix->boxb, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
+                    &ix->boxxy, &ix->boxz, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
                     &ix->bfirst, &ix->blast})
         b->release();
     delete ix;
@@ -418,11 +415,11 @@ int tds_query_create(tds_index *ix, tds_query **out) {
 
 void tds_query_destroy(tds_query *q) {
     if (!q) return;
-    if (q->pending && q->stream) (void)hipStreamSynchronize(q->stream);
+    if (q->pending) (void)hipStreamSynchronize(q->stream);
     for (DBuf *b : {&q->rec, &q->box, &q->rec_s, &q->box_s, &q->first, &q->last, &q->first_s,
-                    &q->last_s, &q->key_in, &q->key_out, &q->val_in, &q->perm, &q->head,
-                    &q->tile_of_head, &q->tiles, &q->items, &q->item_off, &q->ctr, &q->sort_tmp,
-                    &q->scan_tmp, &q->qstage, &q->hits, &q->out_stage})
+                    &q->last_s, &q->key, &q->perm, &q->bcount, &q->bj2, &q->bcursor, &q->bq_off,
+                    &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
+                    &q->hits, &q->out_stage})
         b->release();
     if (q->host_ctr) (void)hipHostFree(q->host_ctr);
     for (auto &ev : q->ev)
@@ -431,43 +428,49 @@ void tds_query_destroy(tds_query *q) {
     delete q;
 }
 
-static int ensure_query_capacity(tds_query *q, int32_t nq) {
-    if (nq <= q->cap_q && q->ctr.p) return TDS_OK;
-    int32_t c = std::max<int32_t>(nq, std::max<int32_t>(1024, q->cap_q + q->cap_q / 2));
-    size_t n = (size_t)c;
-    HIP_TRY(q->rec.ensure(n * sizeof(QRec64)));
-    HIP_TRY(q->rec_s.ensure(n * sizeof(QRec64)));
-    HIP_TRY(q->box.ensure(n * sizeof(QBox32)));
-    HIP_TRY(q->box_s.ensure(n * sizeof(QBox32)));
-    for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->val_in, &q->perm, &q->head,
-                    &q->tile_of_head, &q->items, &q->item_off})
-        HIP_TRY(b->ensure(n * 4));
-    HIP_TRY(q->key_in.ensure(n * 8));
-    HIP_TRY(q->key_out.ensure(n * 8));
-    HIP_TRY(q->tiles.ensure(n * sizeof(Tile)));
-    HIP_TRY(q->ctr.ensure(sizeof(Counters)));
-    size_t sb = 0, cb = 0;
-    HIP_TRY(sort_temp_bytes(c, &sb));
-    HIP_TRY(scan_temp_bytes(c, &cb));
-    HIP_TRY(q->sort_tmp.ensure(sb));
-    HIP_TRY(q->scan_tmp.ensure(cb));
-    q->sort_bytes = q->sort_tmp.bytes;
-    q->scan_bytes = q->scan_tmp.bytes;
-    q->cap_q = c;
+// Query-side buffers for nq segments and nbuckets buckets (grown, never shrunk).
+static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
+    if (nq > q->cap_q || !q->ctr.p) {
+        int32_t c = std::max<int32_t>(nq, std::max<int32_t>(1024, q->cap_q + q->cap_q / 2));
+        size_t n = (size_t)c, n1 = n + 1;
+        HIP_TRY(q->rec.ensure(n * sizeof(QRec64)));
+        HIP_TRY(q->rec_s.ensure(n1 * sizeof(QRec64)));
+        HIP_TRY(q->box.ensure(n * sizeof(QBox32)));
+        HIP_TRY(q->box_s.ensure((n + 4) * sizeof(QBox32)));  // read-ahead slots
+        for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->key, &q->perm})
+            HIP_TRY(b->ensure(n * 4));
+        HIP_TRY(q->tiles.ensure(n1 * sizeof(Tile)));
+        HIP_TRY(q->units.ensure(n1 * 8));
+        HIP_TRY(q->unit_off.ensure(n1 * 8));
+        HIP_TRY(q->ctr.ensure(sizeof(Counters)));
+        q->cap_q = c;
+    }
+    if (nbuckets > q->cap_buckets) {
+        size_t n = (size_t)nbuckets;
+        for (DBuf *b : {&q->bcount, &q->bj2, &q->bcursor, &q->bq_off}) HIP_TRY(b->ensure(n * 4));
+        q->cap_buckets = nbuckets;
+    }
     return TDS_OK;
 }
 
-static int default_grid(int block) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return cus * std::max(1, 2048 / block);
-}
-
-static int launch_pair_now(tds_query *q) {
-    HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->grid,
-                        (q->opts.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0, q->hits.as<Hit24>(),
-                        q->cap_hits, q->stream));
+// Pair kernel (selects pairs) then refine kernel (turns them into hits), with
+// HIP events around each when timing is on. pair = 0 runs the refine only.
+static int launch_search(tds_query *q, bool pair) {
+    const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
+    if (timing) HIP_TRY(hipEventRecord(q->ev[1], q->stream));
+    if (pair) {
+        int used = 0;
+        HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->opts.grid,
+                            (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0, q->cand.as<Cand>(),
+                            q->cap_cand, q->stream, &used));
+        q->grid = used;
+    }
+    if (timing) HIP_TRY(hipEventRecord(q->ev[2], q->stream));
+    HIP_TRY(launch_refine(q->b, q->ix->dev, q->cand.as<Cand>(), q->cap_cand, q->hits.as<Hit24>(),
+                          q->cap_hits, q->stream));
+    if (timing) HIP_TRY(hipEventRecord(q->ev[3], q->stream));
+    HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
+                           q->stream));
     return TDS_OK;
 }
 
@@ -485,8 +488,9 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     if (o.tiling != TDS_TILE_PERIODIC && o.tiling != TDS_TILE_RANGE)
         return fail(TDS_EINVAL, "tds_query_batch: unknown tiling %d", o.tiling);
     if (o.batch_size == 0) o.batch_size = 128;
-    if (o.batch_size < 1 || o.batch_size > 4096)
-        return fail(TDS_EINVAL, "tds_query_batch: batch_size %d out of 1..4096", o.batch_size);
+    if (o.batch_size < 1 || o.batch_size > 65536)
+        return fail(TDS_EINVAL, "tds_query_batch: batch_size %d out of 1..65536", o.batch_size);
+    if (o.reserved0 != 0) return fail(TDS_EINVAL, "tds_query_batch: reserved0 must be 0");
     if (o.block_size == 0) o.block_size = 256;
     if (o.block_size != 64 && o.block_size != 128 && o.block_size != 256 && o.block_size != 512 &&
         o.block_size != 1024)
@@ -505,16 +509,22 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     }
 
     hipStream_t st = (hipStream_t)stream;
+    const tds_index *ix = q->ix;
+    const int nbuckets = nbuckets_for(o.tiling, ix->dev.nb, ix->dev.m);
     q->stream = st;
     q->opts = o;
     q->block = o.block_size;
-    q->grid = o.grid ? o.grid : default_grid(o.block_size);
-    int rc = ensure_query_capacity(q, std::max<int32_t>(nq, 1));
+    int rc = ensure_capacity(q, std::max<int32_t>(nq, 1), nbuckets);
     if (rc) return rc;
     unsigned long long want = o.capacity > 0 ? (unsigned long long)o.capacity : (1ull << 20);
     if (q->cap_hits < want || !q->hits.p) {
         HIP_TRY(q->hits.ensure(want * sizeof(Hit24)));
         q->cap_hits = q->hits.bytes / sizeof(Hit24);
+    }
+    unsigned long long want_cand = std::max<unsigned long long>(want, 1ull << 22);
+    if (q->cap_cand < want_cand || !q->cand.p) {
+        HIP_TRY(q->cand.ensure(want_cand * sizeof(Cand)));
+        q->cap_cand = q->cand.bytes / sizeof(Cand);
     }
 
     const double *qin[8];
@@ -536,62 +546,39 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     DevBatch &b = q->b;
     b.nq = nq;
     b.s = o.batch_size;
-    b.tiling = o.tiling;
     b.chunk = chunk_for(o.mode, o.block_size);
+    b.tiling = o.tiling;
+    b.nbuckets = nbuckets;
+    b.ntiles_cap = o.tiling == TDS_TILE_PERIODIC ? (nq + o.batch_size - 1) / o.batch_size : nq;
+    b.count_overlap = (o.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0;
     b.rec = q->rec.as<QRec64>();
-    b.box = q->box.as<QBox32>();
     b.rec_s = q->rec_s.as<QRec64>();
+    b.box = q->box.as<QBox32>();
     b.box_s = q->box_s.as<QBox32>();
     b.first = q->first.as<int32_t>();
     b.last = q->last.as<int32_t>();
     b.first_s = q->first_s.as<int32_t>();
     b.last_s = q->last_s.as<int32_t>();
-    b.key_in = q->key_in.as<unsigned long long>();
-    b.key_out = q->key_out.as<unsigned long long>();
-    b.val_in = q->val_in.as<int32_t>();
+    b.key = q->key.as<int32_t>();
     b.perm = q->perm.as<int32_t>();
-    b.head = q->head.as<int32_t>();
-    b.tile_of_head = q->tile_of_head.as<int32_t>();
+    b.bcount = q->bcount.as<int32_t>();
+    b.bj2 = q->bj2.as<int32_t>();
+    b.bcursor = q->bcursor.as<int32_t>();
+    b.bq_off = q->bq_off.as<int32_t>();
     b.tiles = q->tiles.as<Tile>();
-    b.items = q->items.as<int32_t>();
-    b.item_off = q->item_off.as<int32_t>();
+    b.units = q->units.as<long long>();
+    b.unit_off = q->unit_off.as<long long>();
     b.ctr = q->ctr.as<Counters>();
 
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
     if (timing) HIP_TRY(hipEventRecord(q->ev[0], st));
-    HIP_TRY(launch_zero_counters(b.ctr, st));
-    if (nq > 0) {
-        const tds_index *ix = q->ix;
-        double span = ix->t_last - ix->t_first;
-        if (!(span > 0.0)) span = 1.0;
-        HIP_TRY(launch_qprep(qin, din, b, ix->dev, ix->t_first, span, st));
-        int end_bit = 32;
-        if (o.tiling == TDS_TILE_RANGE) {
-            unsigned long long maxkey =
-                (unsigned long long)ix->dev.nb * ((unsigned long long)ix->dev.nb + 1ull);
-            end_bit = 1;
-            while (end_bit < 64 && (maxkey >> end_bit) != 0ull) ++end_bit;
-        }
-        HIP_TRY(launch_sort(q->sort_tmp.p, q->sort_bytes, b, end_bit, st));
-        HIP_TRY(launch_gather(b, ix->dev, st));
-        if (o.tiling == TDS_TILE_RANGE)
-            HIP_TRY(launch_scan(q->scan_tmp.p, q->scan_bytes, b.head, b.tile_of_head, nq, st));
-        HIP_TRY(launch_tiles(b, st));
-        HIP_TRY(launch_scan(q->scan_tmp.p, q->scan_bytes, b.items, b.item_off, nq, st));
-        if (timing) HIP_TRY(hipEventRecord(q->ev[1], st));
-        rc = launch_pair_now(q);
-        if (rc) return rc;
-        if (timing) HIP_TRY(hipEventRecord(q->ev[2], st));
-    } else if (timing) {
-        HIP_TRY(hipEventRecord(q->ev[1], st));
-        HIP_TRY(hipEventRecord(q->ev[2], st));
-    }
-    HIP_TRY(hipMemcpyAsync(q->host_ctr, b.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st));
+    rc = launch_search(q, true);
+    if (rc) return rc;
     q->pending = true;
     q->fetched = false;
     std::memset(&q->stats, 0, sizeof q->stats);
     q->stats.n_query = nq;
-    q->stats.grid = q->grid;
     return TDS_OK;
 }
 
@@ -607,45 +594,52 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
         Counters c = *q->host_ctr;
         if (c.err) {
             q->pending = false;
-            return fail(TDS_EINVAL, "tds_fetch_results: the batch holds an invalid query segment "
-                                    "(non-finite value, t_end <= t_start, or d < 0)");
+            return fail(TDS_EINVAL, "tds_fetch_results: the batch holds an invalid query "
+                                    "segment (non-finite value, t_end <= t_start, or d < 0)");
         }
+        // Overflow (Sec. 5: re-attempt with more memory): a full selected-pair
+        // list re-runs both kernels, a full hit buffer only the refine.
         int retries = 0;
-        while (c.hits > q->cap_hits) {
+        while (c.cand > q->cap_cand || c.hits > q->cap_hits) {
             if (retries >= q->opts.max_retries) {
                 q->pending = false;
-                return fail(TDS_EOVERFLOW, "tds_fetch_results: %llu hits exceed capacity %llu",
-                            c.hits, q->cap_hits);
+                return fail(TDS_EOVERFLOW,
+                            "tds_fetch_results: %llu selected pairs / %llu hits exceed capacity "
+                            "%llu / %llu",
+                            c.cand, c.hits, q->cap_cand, q->cap_hits);
             }
             ++retries;
-            unsigned long long need = c.hits + c.hits / 4 + 1024;
-            HIP_TRY(q->hits.ensure(need * sizeof(Hit24)));
-            q->cap_hits = q->hits.bytes / sizeof(Hit24);
-            // Counters the pair kernel accumulates start again from zero.
-            Counters keep = c;
-            keep.hits = keep.refine = keep.overlap = 0;
-            HIP_TRY(hipMemcpyAsync(q->b.ctr, &keep, sizeof(Counters), hipMemcpyHostToDevice, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (q->opts.flags & TDS_QF_TIMING) HIP_TRY(hipEventRecord(q->ev[1], st));
-            int rc = launch_pair_now(q);
+            const bool again = c.cand > q->cap_cand;
+            if (again) {
+                unsigned long long need = c.cand + c.cand / 4 + 1024;
+                HIP_TRY(q->cand.ensure(need * sizeof(Cand)));
+                q->cap_cand = q->cand.bytes / sizeof(Cand);
+            }
+            if (c.hits > q->cap_hits) {
+                unsigned long long need = c.hits + c.hits / 4 + 1024;
+                HIP_TRY(q->hits.ensure(need * sizeof(Hit24)));
+                q->cap_hits = q->hits.bytes / sizeof(Hit24);
+            }
+            HIP_TRY(launch_reset_counters(q->b.ctr, again ? 1 : 0, st));
+            int rc = launch_search(q, again);
             if (rc) return rc;
-            if (q->opts.flags & TDS_QF_TIMING) HIP_TRY(hipEventRecord(q->ev[2], st));
-            HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             c = *q->host_ctr;
         }
         tds_stats &s = q->stats;
         s.n_eval = (int64_t)c.n_eval;
-        s.n_overlap = (int64_t)c.n_overlap_exact;
-        s.n_overlap_k = (q->opts.flags & TDS_QF_COUNT_OVERLAP) ? (int64_t)c.overlap : -1;
-        s.n_refine = q->opts.mode == TDS_MODE_FP32_REFINE ? (int64_t)c.refine : -1;
+        s.n_overlap = (q->opts.flags & TDS_QF_COUNT_OVERLAP) ? (int64_t)c.n_overlap_exact : -1;
+        s.n_overlap_k = (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? (int64_t)c.overlap : -1;
+        s.n_refine = (int64_t)c.cand;
         s.n_hit = (int64_t)c.hits;
         s.n_tiles = (int64_t)c.n_tiles;
+        s.n_items = (int64_t)c.n_units;
+        s.grid = q->grid;
         s.retries = retries;
-        s.n_items = (int64_t)c.n_items;
         if (q->opts.flags & TDS_QF_TIMING) {
             HIP_TRY(hipEventElapsedTime(&s.ms_prep, q->ev[0], q->ev[1]));
             HIP_TRY(hipEventElapsedTime(&s.ms_pair, q->ev[1], q->ev[2]));
+            HIP_TRY(hipEventElapsedTime(&s.ms_refine, q->ev[2], q->ev[3]));
         }
         q->pending = false;
         q->fetched = true;
@@ -655,7 +649,7 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
     int64_t m = std::min<int64_t>(cap, n);
     if (m > 0) {
         bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
-        if (timing) HIP_TRY(hipEventRecord(q->ev[0], st));
+        if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
         if (out_mem == TDS_MEM_DEVICE) {
             HIP_TRY(launch_translate(q->hits.as<Hit24>(), m, q->b.perm, q->ix->dev, out, st));
         } else {
@@ -664,9 +658,9 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
             HIP_TRY(hipMemcpyAsync(out, q->out_stage.p, (size_t)m * sizeof(tds_hit),
                                    hipMemcpyDeviceToHost, st));
         }
-        if (timing) HIP_TRY(hipEventRecord(q->ev[3], st));
+        if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (timing) HIP_TRY(hipEventElapsedTime(&q->stats.ms_fetch, q->ev[0], q->ev[3]));
+        if (timing) HIP_TRY(hipEventElapsedTime(&q->stats.ms_fetch, q->ev[4], q->ev[5]));
     }
     return TDS_OK;
 }

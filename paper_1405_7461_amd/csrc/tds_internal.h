@@ -17,17 +17,34 @@ struct QRec64 {
     double pad;
 };
 
-// Conservative binary32 box of a query segment: span rounded outward and
-// spatial bounding box widened by d + band and rounded outward (32 bytes).
+// Conservative binary32 box of a query segment: spatial bounding box widened
+// by d + band and rounded outward, plus its span rounded outward (32 bytes).
 struct alignas(32) QBox32 {
-    float t0, t1;
     float xlo, xhi, ylo, yhi, zlo, zhi;
+    float t0, t1;
 };
 
 // A tile: sorted query segments [q0, q0 + nq) against entries [e0, e0 + ne).
+// The entries are cut into nchunk chunks of echunk entries (a multiple of 64,
+// the last chunk shorter); one work unit is one query segment against one
+// chunk, so a tile holds nchunk * nq units, query-fastest.
 struct Tile {
     int32_t q0, nq;
     int32_t e0, ne;
+    int32_t nchunk, echunk;
+    int32_t pad0, pad1;
+};
+
+// Entries per chunk when ne entries are cut into nchunk chunks: as even as
+// possible, rounded up to whole waves of 64.
+__host__ __device__ inline int chunk_entries(int ne, int nchunk) {
+    int per = (ne + nchunk - 1) / (nchunk > 0 ? nchunk : 1);
+    return (per + 63) & ~63;
+}
+
+// A pair selected by the pair kernel (sorted query / sorted entry positions).
+struct Cand {
+    uint32_t q, e;
 };
 
 // Device result record: positions in sorted query / sorted entry order.
@@ -36,16 +53,17 @@ struct Hit24 {
     double ta, tb;
 };
 
-// Device counters of one batch (zeroed before the pair kernel).
+// Device counters of one batch (zeroed at the start of the batch).
 struct Counters {
     unsigned long long hits;
-    unsigned long long refine;
+    unsigned long long cand;     // pairs selected by the pair kernel
     unsigned long long overlap;
     unsigned long long n_eval;
     unsigned long long n_overlap_exact;
-    unsigned int err;           // bit 0: invalid query segment
+    unsigned long long n_units;  // work units of the pair kernel
+    unsigned int err;            // bit 0: invalid query segment
     unsigned int n_tiles;
-    unsigned int n_items;
+    unsigned int n_sorted;       // query segments placed in tiles
     unsigned int pad;
 };
 
@@ -53,14 +71,14 @@ struct Counters {
 struct DevIndex {
     int64_t n;
     int32_t nb;  // non-empty bins
-    int32_t pad;
+    int32_t m;   // bins as requested
+    double t_first, width;
     const double *t0, *t1, *x0, *y0, *z0, *vx, *vy, *vz;
-    const float4 *boxa;   // (t0 down, t1 up, xlo down, xhi up)
-    const float4 *boxb;   // (ylo down, yhi up, zlo down, zhi up)
+    const float4 *boxxy;  // (xlo, xhi, ylo, yhi), rounded outward
+    const float2 *boxz;   // (zlo, zhi), rounded outward
     const int32_t *orig;  // caller index of each sorted entry
     const int64_t *traj;  // trajectory id of each sorted entry
-    const double *t0s;    // t_start, sorted (for overlap counts)
-    const double *t1s;    // t_end, sorted independently
+    const double *t1s;    // t_end, sorted independently (overlap counts)
     const double *bstart, *bpend;  // per non-empty bin: min t_start, prefix max of t_end
     const int32_t *bfirst, *blast;
     double band_rel;      // box slack per unit of (d + query extent + ext_max)
@@ -69,25 +87,29 @@ struct DevIndex {
     double mag_max;       // largest |coordinate| of an entry end point
 };
 
+// Range buckets per first candidate bin: spans of 0, 1, 2 and >= 3 bins.
+constexpr int kSpanClasses = 4;
+
 // Query-side buffers of one batch (device).
 struct DevBatch {
     int32_t nq;
-    int32_t s;            // tile size
+    int32_t s;            // periodic tile size
+    int32_t chunk;        // entries per chunk (at most)
     int32_t tiling;
-    int32_t chunk;
-    QRec64 *rec;          // caller order
-    QBox32 *box;          // caller order
-    QRec64 *rec_s;        // sorted order
-    QBox32 *box_s;        // sorted order
+    int32_t nbuckets;
+    int32_t ntiles_cap;
+    int32_t count_overlap;      // exact overlap count in the query preparation
+    int32_t pad;
+    QRec64 *rec, *rec_s;  // caller order, sorted order (+1 padding slot)
+    QBox32 *box, *box_s;
     int32_t *first, *last;      // caller order candidate range (last < first: empty)
     int32_t *first_s, *last_s;  // sorted order
-    unsigned long long *key_in, *key_out;
-    int32_t *val_in, *perm;     // perm[sorted position] = caller index
-    int32_t *head;              // tile-head flags, then their exclusive scan
-    int32_t *tile_of_head;
+    int32_t *key;               // caller order bucket (-1: no candidates)
+    int32_t *perm;              // perm[sorted position] = caller index
+    int32_t *bcount, *bj2, *bcursor, *bq_off;  // per bucket
     Tile *tiles;
-    int32_t *items;             // work items per tile (zero past the last tile)
-    int32_t *item_off;          // exclusive scan of items
+    long long *units;           // per tile (periodic)
+    long long *unit_off;        // exclusive scan of units per tile (+ total)
     Counters *ctr;
 };
 
@@ -96,24 +118,21 @@ enum : int { kTilePeriodic = 0, kTileRange = 1 };
 
 // Launchers (tds_kernels.hip). All enqueue on `st`, return hipError_t.
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
-                         const int64_t *traj_raw, DevIndex ix, double *t0, double *t1, double *x0,
-                         double *y0, double *z0, double *vx, double *vy, double *vz, float4 *boxa,
-                         float4 *boxb, int32_t *orig, int64_t *traj, hipStream_t st);
-hipError_t launch_qprep(const double *const *q, const double *d, DevBatch b, DevIndex ix,
-                        double t_first, double t_span, hipStream_t st);
-hipError_t sort_temp_bytes(int n, size_t *bytes);
-hipError_t launch_sort(void *temp, size_t temp_bytes, DevBatch b, int end_bit, hipStream_t st);
-hipError_t launch_gather(DevBatch b, DevIndex ix, hipStream_t st);
-hipError_t scan_temp_bytes(int n, size_t *bytes);
-hipError_t launch_scan(void *temp, size_t temp_bytes, const int32_t *in, int32_t *out, int n,
-                       hipStream_t st);
-hipError_t launch_tiles(DevBatch b, hipStream_t st);
-hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int count_overlap,
-                       Hit24 *out, unsigned long long cap, hipStream_t st);
+                         const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
+                         double *z0, double *vx, double *vy, double *vz, float4 *boxxy,
+                         float2 *boxz, int32_t *orig, int64_t *traj, hipStream_t st);
+hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
+                          hipStream_t st);
+// grid <= 0: one workgroup per resident slot (persistent launch); the grid
+// actually launched is written to *grid_used.
+hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int kernel_overlap,
+                       Cand *cand, unsigned long long cap, hipStream_t st, int *grid_used);
+hipError_t launch_refine(DevBatch b, DevIndex ix, const Cand *cand, unsigned long long cand_cap,
+                         Hit24 *out, unsigned long long cap, hipStream_t st);
 hipError_t launch_translate(const Hit24 *in, int64_t n, const int32_t *perm, DevIndex ix,
                             void *out_hits, hipStream_t st);
-hipError_t launch_zero_counters(Counters *c, hipStream_t st);
-int ept_for(int mode, int block);
+hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
 int chunk_for(int mode, int block);
+int nbuckets_for(int tiling, int nb, int m);
 
 }  // namespace tds

@@ -1,13 +1,16 @@
 // HIP kernels of the distance-threshold search for CDNA4 (gfx950).
 //
-// Data layout: entries are sorted by t_start and stored as a structure of
-// arrays (coalesced 64-lane loads); query segments of a batch are sorted,
-// grouped into tiles and read wave-uniformly (scalar loads); one lane holds
-// EPT entries of a work item and walks the tile's query segments.
+// Layout: entries sorted by t_start as a structure of arrays (one lane per
+// entry, coalesced 64-lane loads); query segments of a batch grouped into
+// tiles by a counting sort on their candidate bin range (or on their t_start
+// bin for the paper's Periodic batches) and read wave-uniformly through the
+// scalar cache; a persistent pair kernel splits the batch's work units
+// (query segment x chunk of candidate entries) evenly over the resident
+// waves, with no atomics and no workgroup barriers.
 //
-// The binary64 decision below follows the paper's Alg. 1 (temporal
-// intersection, then the time interval within d from the degree-two
-// polynomial of the squared distance) in one fixed evaluation order:
+// The binary64 decision follows the paper's Alg. 1 (temporal intersection,
+// then the time interval within d from the degree-two polynomial of the
+// squared distance) in one fixed evaluation order:
 //   tlo = max(q.t0, e.t0), thi = min(q.t1, e.t1), compared only if tlo < thi
 //   T = thi - tlo, tq = tlo - q.t0, te = tlo - e.t0
 //   D_k = fma(q.v_k, tq, q.p0_k) - fma(e.v_k, te, e.p0_k), V_k = q.v_k - e.v_k
@@ -17,7 +20,7 @@
 //         || (B < 0 && fma(a,T,B) > 0 && fma(B,B,-(a*c)) >= 0)
 // Built with -ffp-contract=off: every fma is explicit, nothing is fused or
 // reassociated behind the source's back.
-#include <hipcub/hipcub.hpp>
+#include <type_traits>
 
 #include "tds_internal.h"
 
@@ -25,8 +28,11 @@ namespace tds {
 
 #define TDS_LAUNCH_CHECK() return hipGetLastError()
 
-__device__ __forceinline__ double dmx(double a, double b) { return a > b ? a : b; }
-__device__ __forceinline__ double dmn(double a, double b) { return a < b ? a : b; }
+// max / min of finite values (the result is one of the operands; the sign
+// of a zero result may differ from a compare-and-select, which no decision
+// below can observe).
+__device__ __forceinline__ double dmx(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double dmn(double a, double b) { return __builtin_fmin(a, b); }
 
 // binary32 neighbours of a binary64 value: largest float <= x, smallest >= x.
 __device__ __forceinline__ float f32_down(double x) {
@@ -40,17 +46,22 @@ __device__ __forceinline__ float f32_up(double x) {
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // --------------------------------------------------------------- ingest
 // One thread per sorted position p: gather the caller's segment perm[p],
-// compute its velocity and its conservative binary32 box.
+// compute its velocity and its conservative binary32 bounding box.
 __global__ void k_ingest(const double *__restrict__ rx0, const double *__restrict__ ry0,
                          const double *__restrict__ rz0, const double *__restrict__ rt0,
                          const double *__restrict__ rx1, const double *__restrict__ ry1,
                          const double *__restrict__ rz1, const double *__restrict__ rt1,
                          int64_t n, const int32_t *__restrict__ perm,
                          const int64_t *__restrict__ traj_raw, double *t0, double *t1, double *x0,
-                         double *y0, double *z0, double *vx, double *vy, double *vz, float4 *boxa,
-                         float4 *boxb, int32_t *orig, int64_t *traj) {
+                         double *y0, double *z0, double *vx, double *vy, double *vz, float4 *boxxy,
+                         float2 *boxz, int32_t *orig, int64_t *traj) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int32_t i = perm[p];
@@ -65,27 +76,45 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
     vx[p] = (a1 - a0) / dt;
     vy[p] = (b1 - b0) / dt;
     vz[p] = (c1 - c0) / dt;
-    boxa[p] = make_float4(f32_down(s0), f32_up(s1), f32_down(dmn(a0, a1)), f32_up(dmx(a0, a1)));
-    boxb[p] = make_float4(f32_down(dmn(b0, b1)), f32_up(dmx(b0, b1)), f32_down(dmn(c0, c1)),
-                          f32_up(dmx(c0, c1)));
+    boxxy[p] = make_float4(f32_down(dmn(a0, a1)), f32_up(dmx(a0, a1)), f32_down(dmn(b0, b1)),
+                           f32_up(dmx(b0, b1)));
+    boxz[p] = make_float2(f32_down(dmn(c0, c1)), f32_up(dmx(c0, c1)));
     orig[p] = i;
     traj[p] = traj_raw ? traj_raw[i] : (int64_t)i;
 }
 
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
-                         const int64_t *traj_raw, DevIndex, double *t0, double *t1, double *x0,
-                         double *y0, double *z0, double *vx, double *vy, double *vz, float4 *boxa,
-                         float4 *boxb, int32_t *orig, int64_t *traj, hipStream_t st) {
+                         const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
+                         double *z0, double *vx, double *vy, double *vz, float4 *boxxy,
+                         float2 *boxz, int32_t *orig, int64_t *traj, hipStream_t st) {
     if (n == 0) return hipSuccess;
     int blk = 256;
     int64_t grid = (n + blk - 1) / blk;
     hipLaunchKernelGGL(k_ingest, dim3((unsigned)grid), dim3(blk), 0, st, raw[0], raw[1], raw[2],
                        raw[3], raw[4], raw[5], raw[6], raw[7], n, perm_sorted, traj_raw, t0, t1, x0,
-                       y0, z0, vx, vy, vz, boxa, boxb, orig, traj);
+                       y0, z0, vx, vy, vz, boxxy, boxz, orig, traj);
     TDS_LAUNCH_CHECK();
 }
 
-// --------------------------------------------------------------- query prep
+// --------------------------------------------------------------- prepare
+int nbuckets_for(int tiling, int nb, int m) {
+    return tiling == kTileRange ? (nb > 0 ? nb * kSpanClasses : 1) : (m > 0 ? m : 1);
+}
+
+// Clears the per-bucket counters and the batch counters.
+__global__ void k_zero_batch(DevBatch b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int k = i; k < b.nbuckets; k += gridDim.x * blockDim.x) {
+        b.bcount[k] = 0;
+        b.bj2[k] = -1;
+        b.bcursor[k] = 0;
+    }
+    if (i == 0) {
+        Counters z = {};
+        *b.ctr = z;
+    }
+}
+
 // First index k in [0, nb) with a[k] > x (a non-decreasing), nb if none.
 __device__ __forceinline__ int first_greater(const double *a, int nb, double x) {
     int lo = 0, hi = nb;
@@ -95,7 +124,7 @@ __device__ __forceinline__ int first_greater(const double *a, int nb, double x) 
     }
     return lo;
 }
-// Number of elements < x in a sorted array.
+// Number of leading elements < x of a non-decreasing array.
 __device__ __forceinline__ int64_t count_less(const double *a, int64_t n, double x) {
     int64_t lo = 0, hi = n;
     while (lo < hi) {
@@ -104,7 +133,7 @@ __device__ __forceinline__ int64_t count_less(const double *a, int64_t n, double
     }
     return lo;
 }
-// Number of elements <= x in a sorted array.
+// Number of leading elements <= x of a non-decreasing array.
 __device__ __forceinline__ int64_t count_leq(const double *a, int64_t n, double x) {
     int64_t lo = 0, hi = n;
     while (lo < hi) {
@@ -114,22 +143,15 @@ __device__ __forceinline__ int64_t count_leq(const double *a, int64_t n, double 
     return lo;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// One thread per query segment (caller order): validate, build its binary64
-// record and binary32 box, find its candidate range with two binary
-// searches over the non-empty bins (Sec. 4: bins whose temporal extent
-// overlaps the segment's), count its overlapping entries, and make its
-// sort key.
+// One thread per query segment (caller order): validate it, build its
+// binary64 record and binary32 box, find its candidate range (Sec. 4: the
+// bins whose temporal extent overlaps its span) with two binary searches
+// over the non-empty bins, and count it into its bucket.
 __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict__ qy0,
                         const double *__restrict__ qz0, const double *__restrict__ qt0,
                         const double *__restrict__ qx1, const double *__restrict__ qy1,
                         const double *__restrict__ qz1, const double *__restrict__ qt1,
-                        const double *__restrict__ qd, DevBatch b, DevIndex ix, double t_first,
-                        double t_span) {
+                        const double *__restrict__ qd, DevBatch b, DevIndex ix) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long novl = 0;
     if (i < b.nq) {
@@ -160,405 +182,595 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         r.pad = 0.0;
         b.rec[i] = r;
 
-        // Box widened by d plus a band that covers the binary64 decision's
-        // own rounding (a hit in binary64 implies the exact distance is
-        // below d + band at some common time) and the rounding of positions.
+        // Box widened by d plus a band covering the binary64 decision's own
+        // rounding (a binary64 hit implies an exact distance below d + band
+        // at some common time) and the rounding of computed positions.
         double ext = fabs(a1 - a0) + fabs(b1 - b0) + fabs(c1 - c0);
         double mag = dmx(dmx(fabs(a0), fabs(a1)), dmx(dmx(fabs(b0), fabs(b1)), dmx(fabs(c0), fabs(c1))));
         double w = d + ix.band_rel * (d + ext + ix.ext_max) +
                    ix.band_abs * (1.0 + d + mag + ext + ix.mag_max + ix.ext_max);
         QBox32 bx;
-        bx.t0 = f32_down(s0);
-        bx.t1 = f32_up(s1);
         bx.xlo = f32_down(dmn(a0, a1) - w);
         bx.xhi = f32_up(dmx(a0, a1) + w);
         bx.ylo = f32_down(dmn(b0, b1) - w);
         bx.yhi = f32_up(dmx(b0, b1) + w);
         bx.zlo = f32_down(dmn(c0, c1) - w);
         bx.zhi = f32_up(dmx(c0, c1) + w);
+        bx.t0 = f32_down(s0);
+        bx.t1 = f32_up(s1);
         b.box[i] = bx;
 
-        // Candidate bins: j1 = first bin whose prefix-max end exceeds t0,
-        // j2 = last bin whose start is below t1 (strict: spans must overlap
-        // with positive length).
+        // Candidate bins: j1 = first bin whose running maximum end exceeds
+        // t0, j2 = last bin whose start is below t1 (spans must overlap with
+        // positive length).
         int j1 = first_greater(ix.bpend, ix.nb, s0);
-        int j2;
-        {
-            int lo = 0, hi = ix.nb;  // number of bins with start < t1
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (ix.bstart[mid] < s1) lo = mid + 1; else hi = mid;
+        int lo = 0, hi = ix.nb;  // number of bins with start < t1
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (ix.bstart[mid] < s1) lo = mid + 1; else hi = mid;
+        }
+        int j2 = lo - 1;
+        bool any = ok && j1 <= j2;
+        b.first[i] = any ? ix.bfirst[j1] : 0;
+        b.last[i] = any ? ix.blast[j2] : -1;
+
+        if (b.count_overlap && ok)
+            novl = (unsigned long long)(count_less(ix.t0, ix.n, s1) - count_leq(ix.t1s, ix.n, s0));
+
+        int key = -1;
+        if (b.tiling == kTileRange) {
+            if (any) {
+                int cls = min(j2 - j1, kSpanClasses - 1);
+                key = j1 * kSpanClasses + cls;
+                if (cls == kSpanClasses - 1) atomicMax(&b.bj2[key], j2);
             }
-            j2 = lo - 1;
-        }
-        int first = 0, last = -1;
-        if (ok && j1 <= j2) {
-            first = ix.bfirst[j1];
-            last = ix.blast[j2];
-        }
-        b.first[i] = first;
-        b.last[i] = last;
-
-        if (ok) novl = (unsigned long long)(count_less(ix.t0s, ix.n, s1) - count_leq(ix.t1s, ix.n, s0));
-
-        unsigned long long key;
-        if (b.tiling == kTilePeriodic) {
-            double u = (s0 - t_first) / t_span;
-            u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-            double k = u * 4294967295.0;
-            key = (unsigned long long)k;
         } else {
-            unsigned long long K = (unsigned long long)ix.nb + 1ull;
-            if (j1 <= j2 && ok)
-                key = (unsigned long long)j1 * K + (unsigned long long)(j2 - j1);
-            else
-                key = (unsigned long long)ix.nb * K;
+            double u = floor((s0 - ix.t_first) / ix.width);
+            key = u <= 0.0 ? 0 : (u >= (double)(b.nbuckets - 1) ? b.nbuckets - 1 : (int)u);
         }
-        b.key_in[i] = key;
-        b.val_in[i] = i;
+        if (key >= 0) atomicAdd(&b.bcount[key], 1);
+        b.key[i] = key;
     }
     novl = wave_sum_u64(novl);
     if (lane_id() == 0 && novl) atomicAdd(&b.ctr->n_overlap_exact, novl);
 }
 
-hipError_t launch_qprep(const double *const *q, const double *d, DevBatch b, DevIndex ix,
-                        double t_first, double t_span, hipStream_t st) {
-    if (b.nq == 0) return hipSuccess;
-    int blk = 256;
-    int grid = (b.nq + blk - 1) / blk;
-    hipLaunchKernelGGL(k_qprep, dim3(grid), dim3(blk), 0, st, q[0], q[1], q[2], q[3], q[4], q[5],
-                       q[6], q[7], d, b, ix, t_first, t_span);
-    TDS_LAUNCH_CHECK();
+// Exclusive scan of one value per thread over a block of BLOCK threads;
+// returns the prefix and writes the block total to *total.
+template <int BLOCK>
+__device__ __forceinline__ long long block_exclusive_scan(long long v, long long *total) {
+    __shared__ long long warp_sums[BLOCK / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    long long incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        long long y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) warp_sums[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        long long s = lane < BLOCK / 64 ? warp_sums[lane] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            long long y = __shfl_up(s, off);
+            if (lane >= off) s += y;
+        }
+        if (lane < BLOCK / 64) warp_sums[lane] = s;  // inclusive over warps
+    }
+    __syncthreads();
+    long long before = w > 0 ? warp_sums[w - 1] : 0;
+    *total = warp_sums[BLOCK / 64 - 1];
+    __syncthreads();
+    return before + incl - v;
 }
 
-// --------------------------------------------------------------- sort
-hipError_t sort_temp_bytes(int n, size_t *bytes) {
-    *bytes = 0;
-    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const unsigned long long *)nullptr,
-                                              (unsigned long long *)nullptr,
-                                              (const int32_t *)nullptr, (int32_t *)nullptr, n, 0,
-                                              64, (hipStream_t)0);
+// Candidate range of a range bucket (all its queries share it).
+__device__ __forceinline__ void bucket_range(const DevBatch &b, const DevIndex &ix, int k,
+                                             int *e0, int *ne) {
+    int j1 = k / kSpanClasses, cls = k - j1 * kSpanClasses;
+    int j2 = cls < kSpanClasses - 1 ? j1 + cls : b.bj2[k];
+    *e0 = ix.bfirst[j1];
+    *ne = ix.blast[j2] - ix.bfirst[j1] + 1;
 }
 
-hipError_t launch_sort(void *temp, size_t temp_bytes, DevBatch b, int end_bit, hipStream_t st) {
-    if (b.nq == 0) return hipSuccess;
-    size_t tb = temp_bytes;
-    return hipcub::DeviceRadixSort::SortPairs(temp, tb, b.key_in, b.key_out, b.val_in, b.perm, b.nq,
-                                              0, end_bit, st);
-}
-
-hipError_t scan_temp_bytes(int n, size_t *bytes) {
-    *bytes = 0;
-    return hipcub::DeviceScan::ExclusiveSum(nullptr, *bytes, (const int32_t *)nullptr,
-                                            (int32_t *)nullptr, n, (hipStream_t)0);
-}
-
-hipError_t launch_scan(void *temp, size_t temp_bytes, const int32_t *in, int32_t *out, int n,
-                       hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    size_t tb = temp_bytes;
-    return hipcub::DeviceScan::ExclusiveSum(temp, tb, in, out, n, st);
-}
-
-// --------------------------------------------------------------- gather
-// One thread per sorted position: move the query's record, box and range
-// into sorted order and flag tile heads (every s-th position, and for range
-// tiling also wherever the candidate bin range changes).
-__global__ void k_gather(DevBatch b) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= b.nq) return;
-    int i = b.perm[p];
-    b.rec_s[p] = b.rec[i];
-    b.box_s[p] = b.box[i];
-    b.first_s[p] = b.first[i];
-    b.last_s[p] = b.last[i];
-    int h = (p % b.s) == 0;
-    if (b.tiling == kTileRange && p > 0 && b.key_out[p] != b.key_out[p - 1]) h = 1;
-    b.head[p] = h;
-}
-
-hipError_t launch_gather(DevBatch b, DevIndex, hipStream_t st) {
-    if (b.nq == 0) return hipSuccess;
-    int blk = 256;
-    hipLaunchKernelGGL(k_gather, dim3((b.nq + blk - 1) / blk), dim3(blk), 0, st, b);
-    TDS_LAUNCH_CHECK();
-}
-
-// --------------------------------------------------------------- tiles
-// One thread per sorted position. A head position writes its tile: the
-// queries up to the next head and the union of their candidate ranges; the
-// number of work items is ceil(range / chunk). Positions past the last tile
-// write zero items so that the item scan can run over nq slots.
-__global__ void k_tiles(DevBatch b) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+// One block: exclusive scan of the bucket counts (sorted offsets). For range
+// tiling each non-empty bucket is a tile of nchunk * nq work units, and the
+// tiles' unit offsets are scanned here as well.
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex ix) {
+    const int n = b.nbuckets;
+    const int per = (n + kScanBlock - 1) / kScanBlock;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    const bool range = b.tiling == kTileRange;
+    long long c_sum = 0, t_sum = 0, u_sum = 0;
     unsigned long long ev = 0;
-    if (p < b.nq) {
-        int n_tiles;
-        int t;
-        if (b.tiling == kTilePeriodic) {
-            n_tiles = (b.nq + b.s - 1) / b.s;
-            t = (p % b.s == 0) ? p / b.s : -1;
-        } else {
-            n_tiles = b.tile_of_head[b.nq - 1] + b.head[b.nq - 1];
-            t = b.head[p] ? b.tile_of_head[p] : -1;
+    for (int k = lo; k < hi; ++k) {
+        int c = b.bcount[k];
+        c_sum += c;
+        if (range && c > 0) {
+            int e0, ne;
+            bucket_range(b, ix, k, &e0, &ne);
+            t_sum += 1;
+            u_sum += (long long)((ne + b.chunk - 1) / b.chunk) * c;
+            ev += (unsigned long long)c * (unsigned long long)ne;
         }
-        if (p >= n_tiles) b.items[p] = 0;
-        if (p == 0) b.ctr->n_tiles = (unsigned)n_tiles;
-        if (t >= 0) {
-            int end = p + 1;
-            while (end < b.nq && end - p < b.s && !b.head[end]) ++end;
-            int lo = 0x7fffffff, hi = -1;
-            for (int k = p; k < end; ++k) {
-                int f = b.first_s[k], l = b.last_s[k];
-                if (l >= f) {
-                    lo = min(lo, f);
-                    hi = max(hi, l);
-                }
-            }
+    }
+    long long c_tot, t_tot, u_tot;
+    long long c_run = block_exclusive_scan<kScanBlock>(c_sum, &c_tot);
+    long long t_run = block_exclusive_scan<kScanBlock>(t_sum, &t_tot);
+    long long u_run = block_exclusive_scan<kScanBlock>(u_sum, &u_tot);
+    for (int k = lo; k < hi; ++k) {
+        int c = b.bcount[k];
+        b.bq_off[k] = (int)c_run;
+        if (range && c > 0) {
+            int e0, ne;
+            bucket_range(b, ix, k, &e0, &ne);
             Tile tl;
-            tl.q0 = p;
-            tl.nq = end - p;
-            tl.e0 = hi >= lo ? lo : 0;
-            tl.ne = hi >= lo ? hi - lo + 1 : 0;
-            b.tiles[t] = tl;
-            b.items[t] = (tl.ne + b.chunk - 1) / b.chunk;
-            ev = (unsigned long long)tl.nq * (unsigned long long)tl.ne;
+            tl.q0 = (int)c_run;
+            tl.nq = c;
+            tl.e0 = e0;
+            tl.ne = ne;
+            tl.nchunk = (ne + b.chunk - 1) / b.chunk;
+            tl.echunk = chunk_entries(ne, tl.nchunk);
+            tl.pad0 = tl.pad1 = 0;
+            b.tiles[t_run] = tl;
+            b.unit_off[t_run] = u_run;
+            t_run += 1;
+            u_run += (long long)tl.nchunk * c;
         }
+        c_run += c;
     }
     ev = wave_sum_u64(ev);
     if (lane_id() == 0 && ev) atomicAdd(&b.ctr->n_eval, ev);
+    if (threadIdx.x == 0) {
+        b.ctr->n_sorted = (unsigned)c_tot;
+        if (range) {
+            b.ctr->n_tiles = (unsigned)t_tot;
+            b.ctr->n_units = (unsigned long long)u_tot;
+            b.unit_off[t_tot] = u_tot;
+        }
+    }
 }
 
-hipError_t launch_tiles(DevBatch b, hipStream_t st) {
-    if (b.nq == 0) return hipSuccess;
-    int blk = 256;
-    hipLaunchKernelGGL(k_tiles, dim3((b.nq + blk - 1) / blk), dim3(blk), 0, st, b);
+// One thread per query segment with candidates: place it at its bucket's
+// next free position and move its record, box and range there.
+__global__ void k_scatter(DevBatch b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.nq) return;
+    int k = b.key[i];
+    if (k < 0) return;
+    int pos = b.bq_off[k] + atomicAdd(&b.bcursor[k], 1);
+    b.perm[pos] = i;
+    b.rec_s[pos] = b.rec[i];
+    b.box_s[pos] = b.box[i];
+    b.first_s[pos] = b.first[i];
+    b.last_s[pos] = b.last[i];
+}
+
+// Periodic tiles (Sec. 6): one wave per tile of s consecutive sorted query
+// segments; the tile's range is the union of its members' ranges.
+__global__ void k_periodic_tiles(DevBatch b) {
+    const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (t >= b.ntiles_cap) return;
+    const int q0 = t * b.s;
+    const int nq = min(b.s, b.nq - q0);
+    int lo = 0x7fffffff, hi = -1;
+    for (int k = lane; k < nq; k += 64) {
+        int f = b.first_s[q0 + k], l = b.last_s[q0 + k];
+        if (l >= f) {
+            lo = min(lo, f);
+            hi = max(hi, l);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+    }
+    if (lane == 0) {
+        Tile tl;
+        tl.q0 = q0;
+        tl.nq = nq;
+        tl.e0 = hi >= lo ? lo : 0;
+        tl.ne = hi >= lo ? hi - lo + 1 : 0;
+        tl.nchunk = (tl.ne + b.chunk - 1) / b.chunk;
+        tl.echunk = chunk_entries(tl.ne, tl.nchunk);
+        tl.pad0 = tl.pad1 = 0;
+        b.tiles[t] = tl;
+        b.units[t] = (long long)tl.nchunk * nq;
+        if (tl.ne > 0) atomicAdd(&b.ctr->n_eval, (unsigned long long)nq * (unsigned long long)tl.ne);
+    }
+}
+
+// One block: exclusive scan of the periodic tiles' work units.
+__global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
+    const int n = b.ntiles_cap;
+    const int per = (n + kScanBlock - 1) / kScanBlock;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    long long s = 0;
+    for (int k = lo; k < hi; ++k) s += b.units[k];
+    long long tot;
+    long long run = block_exclusive_scan<kScanBlock>(s, &tot);
+    for (int k = lo; k < hi; ++k) {
+        b.unit_off[k] = run;
+        run += b.units[k];
+    }
+    if (threadIdx.x == 0) {
+        b.ctr->n_tiles = (unsigned)n;
+        b.ctr->n_units = (unsigned long long)tot;
+        b.unit_off[n] = tot;
+    }
+}
+
+hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
+                          hipStream_t st) {
+    const int blk = 256;
+    int zgrid = (b.nbuckets + blk - 1) / blk;
+    zgrid = zgrid < 1 ? 1 : (zgrid > 1024 ? 1024 : zgrid);
+    hipLaunchKernelGGL(k_zero_batch, dim3(zgrid), dim3(blk), 0, st, b);
+    if (b.nq == 0) TDS_LAUNCH_CHECK();
+    const int qgrid = (b.nq + blk - 1) / blk;
+    hipLaunchKernelGGL(k_qprep, dim3(qgrid), dim3(blk), 0, st, q[0], q[1], q[2], q[3], q[4], q[5],
+                       q[6], q[7], d, b, ix);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanBlock), 0, st, b, ix);
+    hipLaunchKernelGGL(k_scatter, dim3(qgrid), dim3(blk), 0, st, b);
+    if (b.tiling == kTilePeriodic) {
+        int waves = b.ntiles_cap;
+        hipLaunchKernelGGL(k_periodic_tiles, dim3((waves * 64 + blk - 1) / blk), dim3(blk), 0, st, b);
+        hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kScanBlock), 0, st, b);
+    }
     TDS_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------------- pair test
-// Kernel arguments of the pair kernel. Uniform tables (query records,
-// tiles, item offsets) are separate restrict-qualified pointers so that
-// their wave-uniform loads can go through the scalar cache.
-struct PairArgs {
-    Hit24 *out;
-    unsigned long long cap;
-    Counters *ctr;
+// The binary64 decision (Sec. 5, Alg. 1: temporal intersection, then the
+// degree-two polynomial of the squared distance) in the pinned order.
+struct Pair64 {
+    double tlo, thi, T, a, B, c;
+    bool in0, inT, hit;
 };
 
-// The binary64 decision and, for hits, the interval (stable roots of the
-// quadratic, clamped to the common span).
-__device__ __forceinline__ bool pair64(const QRec64 &q, double et0, double et1, double ex0,
-                                       double ey0, double ez0, double evx, double evy, double evz,
-                                       bool *ovl, double *ta, double *tb, bool want_interval) {
-    double tlo = dmx(q.t0, et0);
-    double thi = dmn(q.t1, et1);
-    *ovl = tlo < thi;
-    if (!*ovl) return false;
-    double T = thi - tlo;
-    double tq = tlo - q.t0;
-    double te = tlo - et0;
-    double Dx = __builtin_fma(q.vx, tq, q.x0) - __builtin_fma(evx, te, ex0);
-    double Dy = __builtin_fma(q.vy, tq, q.y0) - __builtin_fma(evy, te, ey0);
-    double Dz = __builtin_fma(q.vz, tq, q.z0) - __builtin_fma(evz, te, ez0);
-    double Vx = q.vx - evx;
-    double Vy = q.vy - evy;
-    double Vz = q.vz - evz;
-    double a = __builtin_fma(Vz, Vz, __builtin_fma(Vy, Vy, Vx * Vx));
-    double B = __builtin_fma(Dz, Vz, __builtin_fma(Dy, Vy, Dx * Vx));
-    double c = __builtin_fma(Dz, Dz, __builtin_fma(Dy, Dy, __builtin_fma(Dx, Dx, -q.dd)));
-    bool in0 = c <= 0.0;
-    bool inT = __builtin_fma(__builtin_fma(a, T, B + B), T, c) <= 0.0;
-    bool vtx = (B < 0.0) && (__builtin_fma(a, T, B) > 0.0) && (__builtin_fma(B, B, -(a * c)) >= 0.0);
-    bool hit = in0 || inT || vtx;
-    if (want_interval && hit) {
-        if (in0 && inT) {
-            *ta = tlo;
-            *tb = thi;
-        } else {
-            double h = __builtin_fma(B, B, -(a * c));
-            if (h < 0.0) h = 0.0;
-            double s = sqrt(h);
-            double qq = (B >= 0.0) ? -(B + s) : (s - B);
-            double r1 = qq / a;
-            double r2 = (qq != 0.0) ? c / qq : r1;
-            double lo = dmn(r1, r2);
-            double hi = dmx(r1, r2);
-            double xa = in0 ? tlo : tlo + dmx(lo, 0.0);
-            double xb = inT ? thi : tlo + dmn(hi, T);
-            if (xa > xb) {
-                double tv = dmn(dmx(-B / a, 0.0), T);
-                xa = tlo + tv;
-                xb = xa;
-            }
-            *ta = xa;
-            *tb = xb;
-        }
+__device__ __forceinline__ Pair64 decide64(const QRec64 &q, double et0, double et1, double ex0,
+                                           double ey0, double ez0, double evx, double evy,
+                                           double evz) {
+    Pair64 p;
+    p.tlo = dmx(q.t0, et0);
+    p.thi = dmn(q.t1, et1);
+    p.hit = p.in0 = p.inT = false;
+    if (!(p.tlo < p.thi)) return p;
+    p.T = p.thi - p.tlo;
+    const double tq = p.tlo - q.t0;
+    const double te = p.tlo - et0;
+    const double Dx = __builtin_fma(q.vx, tq, q.x0) - __builtin_fma(evx, te, ex0);
+    const double Dy = __builtin_fma(q.vy, tq, q.y0) - __builtin_fma(evy, te, ey0);
+    const double Dz = __builtin_fma(q.vz, tq, q.z0) - __builtin_fma(evz, te, ez0);
+    const double Vx = q.vx - evx;
+    const double Vy = q.vy - evy;
+    const double Vz = q.vz - evz;
+    p.a = __builtin_fma(Vz, Vz, __builtin_fma(Vy, Vy, Vx * Vx));
+    p.B = __builtin_fma(Dz, Vz, __builtin_fma(Dy, Vy, Dx * Vx));
+    p.c = __builtin_fma(Dz, Dz, __builtin_fma(Dy, Dy, __builtin_fma(Dx, Dx, -q.dd)));
+    p.in0 = p.c <= 0.0;
+    p.inT = __builtin_fma(__builtin_fma(p.a, p.T, p.B + p.B), p.T, p.c) <= 0.0;
+    const bool vtx = (p.B < 0.0) && (__builtin_fma(p.a, p.T, p.B) > 0.0) &&
+                     (__builtin_fma(p.B, p.B, -(p.a * p.c)) >= 0.0);
+    p.hit = p.in0 || p.inT || vtx;
+    return p;
+}
+
+__device__ __forceinline__ bool overlaps64(const QRec64 &q, double et0, double et1) {
+    return dmx(q.t0, et0) < dmn(q.t1, et1);
+}
+
+// Interval of a hit: [tlo, thi] when within d at both ends (convexity),
+// else the stable roots of the quadratic clamped to the common span,
+// collapsed to the clamped vertex if rounding crosses them.
+__device__ __forceinline__ void interval64(const Pair64 &p, double *ta, double *tb) {
+    if (p.in0 && p.inT) {
+        *ta = p.tlo;
+        *tb = p.thi;
+        return;
     }
-    return hit;
+    double h = __builtin_fma(p.B, p.B, -(p.a * p.c));
+    if (h < 0.0) h = 0.0;
+    const double s = sqrt(h);
+    const double qq = (p.B >= 0.0) ? -(p.B + s) : (s - p.B);
+    const double r1 = qq / p.a;
+    const double r2 = (qq != 0.0) ? p.c / qq : r1;
+    const double lo = dmn(r1, r2);
+    const double hi = dmx(r1, r2);
+    double xa = p.in0 ? p.tlo : p.tlo + dmx(lo, 0.0);
+    double xb = p.inT ? p.thi : p.tlo + dmn(hi, p.T);
+    if (xa > xb) {
+        const double tv = dmn(dmx(-p.B / p.a, 0.0), p.T);
+        xa = p.tlo + tv;
+        xb = xa;
+    }
+    *ta = xa;
+    *tb = xb;
 }
 
 // Wave-aggregated append: one atomic per wave, lanes place their records by
-// their rank among the wave's hit lanes. Records past `cap` are counted but
-// not stored (the host re-runs with a larger buffer).
-__device__ __forceinline__ void emit(bool hit, uint32_t q, uint32_t e, double ta, double tb,
-                                     Hit24 *__restrict__ out, unsigned long long cap,
-                                     Counters *__restrict__ ctr) {
-    unsigned long long m = __ballot(hit);
+// their rank among the wave's flagged lanes. Records past `cap` are counted
+// but not stored (the host re-runs with a larger buffer).
+template <class R>
+__device__ __forceinline__ void append(bool flag, const R &rec, R *__restrict__ buf,
+                                       unsigned long long cap, unsigned long long *counter) {
+    const unsigned long long m = __ballot(flag);
     if (m == 0ull) return;
-    unsigned lane = lane_id();
-    int leader = __ffsll((long long)m) - 1;
+    const unsigned lane = lane_id();
+    const int leader = __ffsll((long long)m) - 1;
     unsigned long long base = 0;
-    if ((int)lane == leader) base = atomicAdd(&ctr->hits, (unsigned long long)__popcll(m));
+    if ((int)lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
     base = __shfl(base, leader);
-    if (hit) {
-        unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        unsigned long long pos = base + rank;
-        if (pos < cap) {
-            Hit24 r;
-            r.q = q;
-            r.e = e;
-            r.ta = ta;
-            r.tb = tb;
-            out[pos] = r;
-        }
+    if (flag) {
+        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        const unsigned long long pos = base + rank;
+        if (pos < cap) buf[pos] = rec;
     }
 }
 
-// Tile of work item `it`: last t with item_off[t] <= it (tiles with zero
-// items share their successor's offset, so this is the tile that owns it).
-__device__ __forceinline__ int tile_of_item(const int32_t *off, int n, int it) {
+// Tile owning work unit u: the last t in [0, n) with off[t] <= u (tiles
+// without units share their successor's offset).
+__device__ __forceinline__ int tile_of_unit(const long long *__restrict__ off, int n, long long u) {
     int lo = 0, hi = n;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (off[mid] <= it) lo = mid + 1; else hi = mid;
+        if (off[mid] <= u) lo = mid + 1; else hi = mid;
     }
     return lo - 1;
 }
 
+// Conservative binary32 box test: do the entry's bounding box and the
+// query's box (widened by d + band) overlap on all three axes? Each bound
+// difference keeps its sign under rounding (a flush of a tiny difference to
+// zero can only let a pair through), so every overlapping pair passes.
+__device__ __forceinline__ bool box_overlap(const float4 &b, const float2 &bz, const QBox32 &q) {
+    const float m1 = fmaxf(fmaxf(b.x - q.xhi, q.xlo - b.y), b.z - q.yhi);
+    const float m2 = fmaxf(fmaxf(q.ylo - b.w, bz.x - q.zhi), q.zlo - bz.y);
+    return fmaxf(m1, m2) <= 0.0f;
+}
+
+struct QBox2 {
+    QBox32 a, b;
+};
+
+// Entries per lane: each wave holds 64 * EPT candidate entries of a chunk.
+#ifndef TDS_EPT32
+#define TDS_EPT32 4
+#endif
+constexpr int ept_for_mode(int mode) { return mode == kModeFP64 ? 2 : TDS_EPT32; }
+int chunk_for(int mode, int) { return 64 * ept_for_mode(mode); }
+
+__device__ __forceinline__ long long rfl64(long long v) {
+    unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+    unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Persistent pair kernel. The batch's work units (one query segment against
+// one chunk of <= 64*EPT candidate entries of its tile) are numbered tile by
+// tile, query-fastest, and wave w of W resident waves takes the contiguous
+// range [w*U/W, (w+1)*U/W): every wave gets the same amount of work and
+// consecutive units of a wave share their chunk, so a wave loads each chunk
+// once. Lane l holds entries c0 + 64*j + l (slot j < EPT); the query records
+// are wave-uniform and come through the scalar cache.
+//
+// The kernel only selects pairs: in binary64 mode the pairs the pinned
+// decision calls hits, in binary32 mode the pairs that survive the box
+// filter. Selected pairs go to a compact list that k_refine turns into hits
+// with their intervals, so neither the interval arithmetic nor the refine's
+// registers weigh on this loop.
 template <int MODE, int BLOCK, int EPT, bool COUNT_OVL>
 __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                                                 const QBox32 *__restrict__ box,
                                                 const Tile *__restrict__ tiles,
-                                                const int32_t *__restrict__ items,
-                                                const int32_t *__restrict__ item_off, int nslots,
-                                                DevIndex ix, Hit24 *__restrict__ out,
-                                                unsigned long long cap, Counters *__restrict__ ctr) {
-    const int tid = threadIdx.x;
-    const int total = item_off[nslots - 1] + items[nslots - 1];
-    if (blockIdx.x == 0 && tid == 0) ctr->n_items = (unsigned)total;
-    unsigned long long ovl_acc = 0, ref_acc = 0;
-    constexpr int CHUNK = BLOCK * EPT;
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        const int t = tile_of_item(item_off, nslots, it);
+                                                const long long *__restrict__ unit_off, DevIndex ix,
+                                                Cand *__restrict__ cand, unsigned long long cap,
+                                                Counters *__restrict__ ctr) {
+    const int lane = threadIdx.x & 63;
+    const long long nwaves = (long long)gridDim.x * (BLOCK / 64);
+    const long long w =
+        (long long)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long total = rfl64((long long)ctr->n_units);
+    const int ntiles = __builtin_amdgcn_readfirstlane((int)ctr->n_tiles);
+    long long u = (w * total) / nwaves;
+    const long long uend = ((w + 1) * total) / nwaves;
+    unsigned long long ovl_acc = 0;
+    int t = u < uend ? tile_of_unit(unit_off, ntiles, u) : 0;
+    while (u < uend) {
         const Tile tl = tiles[t];
-        const int c = it - item_off[t];
-        const int eb = tl.e0 + c * CHUNK;
-        const int ee = min(tl.e0 + tl.ne, eb + CHUNK);
+        const long long base = unit_off[t];
+        const long long tend = min(uend, base + (long long)tl.nchunk * tl.nq);
+        while (u < tend) {
+            const long long local = u - base;
+            const int ch = (int)(local / tl.nq);
+            const int qf = (int)(local - (long long)ch * tl.nq);
+            const int ql = (int)min((long long)tl.nq, qf + (tend - u));
+            const int qb = tl.q0 + qf, qe = tl.q0 + ql;
+            const int wb = tl.e0 + ch * tl.echunk;
+            const int we = min(tl.e0 + tl.ne, wb + tl.echunk);
+            const int nv = min(EPT, (we - wb + 63) >> 6);  // slots holding entries (>= 1)
+            u += ql - qf;
 
-        if constexpr (MODE == kModeFP64) {
-            double et0[EPT], et1[EPT], ex0[EPT], ey0[EPT], ez0[EPT], evx[EPT], evy[EPT], evz[EPT];
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                int e = eb + j * BLOCK + tid;
-                if (e < ee) {
-                    et0[j] = ix.t0[e];
-                    et1[j] = ix.t1[e];
-                    ex0[j] = ix.x0[e];
-                    ey0[j] = ix.y0[e];
-                    ez0[j] = ix.z0[e];
-                    evx[j] = ix.vx[e];
-                    evy[j] = ix.vy[e];
-                    evz[j] = ix.vz[e];
-                } else {  // an empty span never overlaps
-                    et0[j] = INFINITY;
-                    et1[j] = -INFINITY;
-                    ex0[j] = ey0[j] = ez0[j] = evx[j] = evy[j] = evz[j] = 0.0;
-                }
-            }
-            for (int qi = 0; qi < tl.nq; ++qi) {
-                const int qs = tl.q0 + qi;
-                const QRec64 q = rec[qs];
+            if constexpr (MODE == kModeFP64) {
+                double et0[EPT], et1[EPT], ex0[EPT], ey0[EPT], ez0[EPT], evx[EPT], evy[EPT],
+                    evz[EPT];
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) {
-                    bool ovl;
-                    double ta = 0.0, tb = 0.0;
-                    bool hit = pair64(q, et0[j], et1[j], ex0[j], ey0[j], ez0[j], evx[j], evy[j],
-                                      evz[j], &ovl, &ta, &tb, true);
-                    if (COUNT_OVL) ovl_acc += __popcll(__ballot(ovl));
-                    emit(hit, (uint32_t)qs, (uint32_t)(eb + j * BLOCK + tid), ta, tb, out, cap, ctr);
-                }
-            }
-        } else {
-            float4 ba[EPT], bb[EPT];
-#pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                int e = eb + j * BLOCK + tid;
-                if (e < ee) {
-                    ba[j] = ix.boxa[e];
-                    bb[j] = ix.boxb[e];
-                } else {  // an empty span never overlaps
-                    ba[j] = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-                    bb[j] = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-                }
-            }
-            for (int qi = 0; qi < tl.nq; ++qi) {
-                const int qs = tl.q0 + qi;
-                const QBox32 qb = box[qs];
-#pragma unroll
-                for (int j = 0; j < EPT; ++j) {
-                    bool tov = (qb.t0 < ba[j].y) & (ba[j].x < qb.t1);
-                    if (COUNT_OVL) ovl_acc += __popcll(__ballot(tov));
-                    bool pass = tov & (ba[j].z <= qb.xhi) & (qb.xlo <= ba[j].w) &
-                                (bb[j].x <= qb.yhi) & (qb.ylo <= bb[j].y) & (bb[j].z <= qb.zhi) &
-                                (qb.zlo <= bb[j].w);
-                    unsigned long long pm = __ballot(pass);
-                    if (pm) {
-                        ref_acc += __popcll(pm);
-                        const QRec64 q = rec[qs];
-                        const int e = eb + j * BLOCK + tid;
-                        bool hit = false;
-                        double ta = 0.0, tb = 0.0;
-                        if (pass) {
-                            bool ovl;
-                            hit = pair64(q, ix.t0[e], ix.t1[e], ix.x0[e], ix.y0[e], ix.z0[e],
-                                         ix.vx[e], ix.vy[e], ix.vz[e], &ovl, &ta, &tb, true);
-                        }
-                        emit(hit, (uint32_t)qs, (uint32_t)e, ta, tb, out, cap, ctr);
+                    const int e = wb + j * 64 + lane;
+                    if (e < we) {
+                        et0[j] = ix.t0[e];
+                        et1[j] = ix.t1[e];
+                        ex0[j] = ix.x0[e];
+                        ey0[j] = ix.y0[e];
+                        ez0[j] = ix.z0[e];
+                        evx[j] = ix.vx[e];
+                        evy[j] = ix.vy[e];
+                        evz[j] = ix.vz[e];
+                    } else {  // an empty span never overlaps
+                        et0[j] = INFINITY;
+                        et1[j] = -INFINITY;
+                        ex0[j] = ey0[j] = ez0[j] = evx[j] = evy[j] = evz[j] = 0.0;
                     }
                 }
+                auto walk = [&](auto full) {
+                    constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
+                    QRec64 qn = rec[qb];
+                    for (int qs = qb; qs < qe; ++qs) {
+                        const QRec64 q = qn;
+                        qn = rec[qs + 1];  // prefetch (the sorted arrays carry one spare slot)
+#pragma unroll
+                        for (int j = 0; j < EPT; ++j) {
+                            if (!FULL && j >= nv) break;  // wave-uniform
+                            const Pair64 p = decide64(q, et0[j], et1[j], ex0[j], ey0[j], ez0[j],
+                                                      evx[j], evy[j], evz[j]);
+                            if (COUNT_OVL) ovl_acc += __popcll(__ballot(p.tlo < p.thi));
+                            append(p.hit, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)}, cand,
+                                   cap, &ctr->cand);
+                        }
+                    }
+                };
+                if (nv == EPT)
+                    walk(std::true_type{});
+                else
+                    walk(std::false_type{});
+            } else {
+                // Conservative binary32 filter: the entry's bounding box against
+                // the query's box widened by d + band; outward rounding on both
+                // sides keeps every binary64 hit. Time is left to the refine.
+                float4 bxy[EPT];
+                float2 bz[EPT];
+#pragma unroll
+                for (int j = 0; j < EPT; ++j) {
+                    const int e = wb + j * 64 + lane;
+                    if (e < we) {
+                        bxy[j] = ix.boxxy[e];
+                        bz[j] = ix.boxz[e];
+                    } else {  // an empty box never passes
+                        bxy[j] = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+                        bz[j] = make_float2(INFINITY, -INFINITY);
+                    }
+                }
+                auto test_query = [&](const QBox32 &qq, const int qs, auto full) {
+                    constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
+                    bool pass[EPT];
+                    bool any = false;
+#pragma unroll
+                    for (int j = 0; j < EPT; ++j) {
+                        pass[j] = false;
+                        if (FULL || j < nv) {  // wave-uniform: skip slots without entries
+                            pass[j] = box_overlap(bxy[j], bz[j], qq);
+                            any |= pass[j];
+                        }
+                    }
+                    if (__ballot(any)) {  // rare: some lane's box overlaps
+#pragma unroll
+                        for (int j = 0; j < EPT; ++j)
+                            append(pass[j], Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)},
+                                   cand, cap, &ctr->cand);
+                    }
+                    if (COUNT_OVL) {
+                        const QRec64 q = rec[qs];
+#pragma unroll
+                        for (int j = 0; j < EPT; ++j) {
+                            const int e = wb + j * 64 + lane;
+                            const bool ov = e < we && overlaps64(q, ix.t0[e], ix.t1[e]);
+                            ovl_acc += __popcll(__ballot(ov));
+                        }
+                    }
+                };
+                auto walk = [&](auto full) {
+                    // Two query boxes (64 B) per scalar load, the next pair
+                    // requested before the current pair is tested.
+                    QBox2 cur = *reinterpret_cast<const QBox2 *>(box + qb);
+                    for (int qs = qb; qs < qe; qs += 2) {
+                        // the sorted arrays carry spare slots past the end
+                        const QBox2 nxt = *reinterpret_cast<const QBox2 *>(box + qs + 2);
+                        test_query(cur.a, qs, full);
+                        if (qs + 1 < qe) test_query(cur.b, qs + 1, full);
+                        cur = nxt;
+                    }
+                };
+                if (nv == EPT)
+                    walk(std::true_type{});
+                else
+                    walk(std::false_type{});
             }
         }
+        ++t;
     }
-    if (lane_id() == 0) {
-        if (COUNT_OVL && ovl_acc) atomicAdd(&ctr->overlap, ovl_acc);
-        if (MODE == kModeFP32Refine && ref_acc) atomicAdd(&ctr->refine, ref_acc);
+    if (COUNT_OVL && lane == 0 && ovl_acc) atomicAdd(&ctr->overlap, ovl_acc);
+}
+
+// Selected pairs -> hits: the pinned binary64 decision again (a selected
+// pair of the binary32 filter may be a miss) and, for hits, the interval.
+// One thread per selected pair, grid-stride over the list.
+__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
+                                                const Cand *__restrict__ cand,
+                                                unsigned long long cand_cap, DevIndex ix,
+                                                Hit24 *__restrict__ out, unsigned long long cap,
+                                                Counters *__restrict__ ctr) {
+    const unsigned long long n = min((unsigned long long)ctr->cand, cand_cap);
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long k0 = (unsigned long long)blockIdx.x * blockDim.x; k0 < n; k0 += stride) {
+        const unsigned long long k = k0 + threadIdx.x;
+        bool hit = false;
+        Hit24 h;
+        if (k < n) {
+            const Cand c = cand[k];
+            const QRec64 q = rec[c.q];
+            const int e = (int)c.e;
+            const Pair64 p = decide64(q, ix.t0[e], ix.t1[e], ix.x0[e], ix.y0[e], ix.z0[e], ix.vx[e],
+                                      ix.vy[e], ix.vz[e]);
+            hit = p.hit;
+            h.q = c.q;
+            h.e = c.e;
+            h.ta = h.tb = 0.0;
+            if (hit) interval64(p, &h.ta, &h.tb);
+        }
+        append(hit, h, out, cap, &ctr->hits);
     }
 }
 
-// Entries per lane and work item for a mode and block size.
-int ept_for(int mode, int block) { return (block >= 512) ? 1 : (mode == kModeFP64 ? 2 : 4); }
-int chunk_for(int mode, int block) { return block * ept_for(mode, block); }
+// Resident waves of a pair-kernel instantiation (grid of the persistent launch).
+template <class K>
+static int resident_blocks(K kernel, int block) {
+    int dev = 0, cus = 256, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
 
 template <int MODE, int BLOCK>
-static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int count_overlap, Hit24 *out,
-                                unsigned long long cap, hipStream_t st) {
-    constexpr int EPT = (BLOCK >= 512) ? 1 : (MODE == kModeFP64 ? 2 : 4);
-    if (count_overlap)
-        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, true>), dim3(grid), dim3(BLOCK), 0, st,
-                           b.rec_s, b.box_s, b.tiles, b.items, b.item_off, b.nq, ix, out, cap, b.ctr);
-    else
-        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, false>), dim3(grid), dim3(BLOCK), 0, st,
-                           b.rec_s, b.box_s, b.tiles, b.items, b.item_off, b.nq, ix, out, cap, b.ctr);
+static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int kernel_overlap, Cand *cand,
+                                unsigned long long cap, hipStream_t st, int *grid_used) {
+    constexpr int EPT = ept_for_mode(MODE);
+    if (kernel_overlap) {
+        auto k = k_pair<MODE, BLOCK, EPT, true>;
+        static const int resident = resident_blocks(k, BLOCK);
+        *grid_used = grid > 0 ? grid : resident;
+        hipLaunchKernelGGL(k, dim3(*grid_used), dim3(BLOCK), 0, st, b.rec_s, b.box_s, b.tiles,
+                           b.unit_off, ix, cand, cap, b.ctr);
+    } else {
+        auto k = k_pair<MODE, BLOCK, EPT, false>;
+        static const int resident = resident_blocks(k, BLOCK);
+        *grid_used = grid > 0 ? grid : resident;
+        hipLaunchKernelGGL(k, dim3(*grid_used), dim3(BLOCK), 0, st, b.rec_s, b.box_s, b.tiles,
+                           b.unit_off, ix, cand, cap, b.ctr);
+    }
     TDS_LAUNCH_CHECK();
 }
 
-hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int count_overlap,
-                       Hit24 *out, unsigned long long cap, hipStream_t st) {
+hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int kernel_overlap,
+                       Cand *cand, unsigned long long cap, hipStream_t st, int *grid_used) {
+    *grid_used = 0;
     if (b.nq == 0) return hipSuccess;
 #define TDS_PAIR_CASE(M, BS) \
-    case BS: return launch_pair_b<M, BS>(b, ix, grid, count_overlap, out, cap, st);
+    case BS: return launch_pair_b<M, BS>(b, ix, grid, kernel_overlap, cand, cap, st, grid_used);
     if (mode == kModeFP64) {
         switch (block) {
             TDS_PAIR_CASE(kModeFP64, 64)
@@ -578,6 +790,30 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
     }
 #undef TDS_PAIR_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_refine(DevBatch b, DevIndex ix, const Cand *cand, unsigned long long cand_cap,
+                         Hit24 *out, unsigned long long cap, hipStream_t st) {
+    if (b.nq == 0) return hipSuccess;
+    static const int grid = resident_blocks(k_refine, 256);
+    hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec_s, cand, cand_cap, ix, out,
+                       cap, b.ctr);
+    TDS_LAUNCH_CHECK();
+}
+
+// Clears the counters that the pair kernel (all = 1) or only the refine
+// kernel (all = 0) accumulates, so they can run again (overflow retry).
+__global__ void k_reset_counters(Counters *c, int all) {
+    c->hits = 0;
+    if (all) {
+        c->cand = 0;
+        c->overlap = 0;
+    }
+}
+
+hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, st, c, all);
+    TDS_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------------- translate
@@ -601,17 +837,6 @@ hipError_t launch_translate(const Hit24 *in, int64_t n, const int32_t *perm, Dev
     int64_t grid = (n + blk - 1) / blk;
     hipLaunchKernelGGL(k_translate, dim3((unsigned)grid), dim3(blk), 0, st, in, n, perm, ix,
                        (int64_t *)out_hits);
-    TDS_LAUNCH_CHECK();
-}
-
-__global__ void k_zero(unsigned *p, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
-}
-
-hipError_t launch_zero_counters(Counters *c, hipStream_t st) {
-    int n = (int)(sizeof(Counters) / sizeof(unsigned));
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (unsigned *)c, n);
     TDS_LAUNCH_CHECK();
 }
 

@@ -15,6 +15,7 @@ def say(*a):
 
 
 def run(db, q, m, index=None, out="host", **opts):
+    opts.setdefault("count_overlap", True)
     ix = index if index is not None else tds.build_index(db, m)
     qh = tds.Query(ix)
     try:

@@ -43,14 +43,12 @@ def test_c1_full(mode, tiling):
     db, q, m = gen.make_config("C1")
     say(f"C1 {mode} {tiling}: db {len(db)} q {len(q)}")
     want = oracle.search(db, q)
-    got, st, _ = run(db, q, m, mode=mode, tiling=tiling, count_overlap=True)
+    got, st, _ = run(db, q, m, mode=mode, tiling=tiling, kernel_overlap=True)
     bit = compare(got, want, db, "C1")
     assert bit
     assert st["n_overlap"] == want.n_overlap
-    if mode == "fp64":
-        assert st["n_overlap_k"] == want.n_overlap
-    else:
-        assert st["n_overlap_k"] >= want.n_overlap
+    assert st["n_overlap_k"] == want.n_overlap
+    if mode == "fp32_refine":
         assert st["n_refine"] >= st["n_hit"]
     assert st["n_eval"] >= st["n_overlap"]
 
@@ -91,13 +89,14 @@ def test_launch_shape_invariance(mode):
     assert len(want) > 200
     for m in (1, 7, 40, 1000):
         ix = tds.build_index(db, m)
-        for block in (64, 256, 1024):
-            for bs in (1, 7, 128, 1000):
+        for block in (64, 128, 256, 512, 1024):
+            for bs, grid in ((1, 0), (7, 1), (128, 3), (1000, 0)):
                 for tiling in ("periodic", "range"):
-                    say(f"invariance {mode} m={m} block={block} bs={bs} {tiling}")
+                    say(f"invariance {mode} m={m} block={block} bs={bs} grid={grid} {tiling}")
                     got, st, _ = run(db, q, m, index=ix, mode=mode, block_size=block,
-                                     batch_size=bs, tiling=tiling)
+                                     batch_size=bs, grid=grid, tiling=tiling)
                     compare(got, want, db, f"m={m} block={block} bs={bs} {tiling}")
+                    assert st["n_overlap"] == want.n_overlap
 
 
 @pytest.mark.parametrize("mode", MODES)
