@@ -208,6 +208,19 @@ def serving_form(log_fn=log, n_requests=400, rates=(0.5, 0.8, 0.95)):
                 saturation_pair_tests_s=sat_pairs, saturation_p50_ms=sat["p50_ms"], rates=runs)
 
 
+def copy_probe(mib: int):
+    """A plain copy kernel of known size: reads and writes MIB MiB each."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log(f"copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +230,9 @@ def main():
     ap.add_argument("--forms", default="fp32_refine,fp64")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the forms, run a plain device copy of MIB MiB three times "
+                         "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search is not "
@@ -250,6 +266,8 @@ def main():
         results[name] = r
         log(f"{name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} pair-tests/s, pair kernel "
             f"{r['pair_ms']:.3f} ms, hits {r['n_hit']}, N_eval {r['n_eval']}")
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
     if "fp32_refine" in results and "fp64" in results:
         assert results["fp32_refine"]["n_hit"] == results["fp64"]["n_hit"]
 

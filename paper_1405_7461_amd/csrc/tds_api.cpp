@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tds.h"
+#include "tds.h"
 #include "tds_internal.h"
 
 using namespace tds;

@@ -664,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             any |= pass[j];
                         }
                     }
-                    if (__ballot(any)) {  // rare: some lane's box overlaps
+                    if (__builtin_expect(__ballot(any) != 0ull, 0)) {  // rare: a box overlaps
 #pragma unroll
                         for (int j = 0; j < EPT; ++j)
                             append(pass[j], Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)},
