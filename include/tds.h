@@ -218,7 +218,9 @@ int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
  * it overflowed (Sec. 5: re-attempt with more memory), translate to caller
  * indices and write min(cap, n) records to `out` (host memory when out_mem is
  * TDS_MEM_HOST, device memory for TDS_MEM_DEVICE). *n_total always receives
- * the number of hits, so cap = 0 sizes the buffer.
+ * the number of hits, so cap = 0 sizes the buffer. Host output is complete on
+ * return; device output is written on the batch's stream (complete on return
+ * only with TDS_QF_TIMING), so work on another stream must wait for it.
  */
 int tds_fetch_results(tds_query *qh, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total);
 int tds_query_stats(const tds_query *qh, tds_stats *out);

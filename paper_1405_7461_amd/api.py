@@ -152,6 +152,7 @@ class Query:
         self._h = h
         self._keep = None
         self._nq = 0
+        self._stream = None
 
     def batch(self, q, d, mode="fp64", tiling="periodic", batch_size=0, block_size=0,
               capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False,
@@ -174,6 +175,7 @@ class Query:
         o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,
                              int(max_retries), int(capacity), int(grid), flags)
         L.check(L.lib().tds_query_batch(self._h, C.byref(s), dptr, C.byref(o), _stream_handle(stream)))
+        self._stream = stream
         self._keep = keep  # device inputs must outlive the batch
         self._nq = int(s.n)
         return self
@@ -189,6 +191,10 @@ class Query:
             if m:
                 L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(buf.data_ptr()), m,
                                                   L.TDS_MEM_DEVICE, C.byref(n)))
+                # the records are written on the batch's stream
+                qs = self._stream
+                if qs is not None and not isinstance(qs, int) and qs != torch.cuda.current_stream():
+                    torch.cuda.current_stream().wait_stream(qs)
             buf = buf[:m]
             res = Hits(buf[:, 0], buf[:, 1], buf[:, 2], buf[:, 3].view(torch.float64),
                        buf[:, 4].view(torch.float64))

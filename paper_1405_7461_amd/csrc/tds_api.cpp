@@ -659,7 +659,9 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
                                    hipMemcpyDeviceToHost, st));
         }
         if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
-        HIP_TRY(hipStreamSynchronize(st));
+        // device output is ordered on the batch's stream; host output and
+        // timing need the copy finished
+        if (timing || out_mem == TDS_MEM_HOST) HIP_TRY(hipStreamSynchronize(st));
         if (timing) HIP_TRY(hipEventElapsedTime(&q->stats.ms_fetch, q->ev[4], q->ev[5]));
     }
     return TDS_OK;

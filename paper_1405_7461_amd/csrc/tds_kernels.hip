@@ -115,6 +115,9 @@ __global__ void k_zero_batch(DevBatch b) {
     }
 }
 
+// Bin tables up to this size (16 bytes per bin) are staged in LDS by k_qprep.
+constexpr int kQprepLdsBins = 2048;
+
 // First index k in [0, nb) with a[k] > x (a non-decreasing), nb if none.
 __device__ __forceinline__ int first_greater(const double *a, int nb, double x) {
     int lo = 0, hi = nb;
@@ -152,6 +155,18 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
                         const double *__restrict__ qx1, const double *__restrict__ qy1,
                         const double *__restrict__ qz1, const double *__restrict__ qt1,
                         const double *__restrict__ qd, DevBatch b, DevIndex ix) {
+    // Small bin tables are searched in LDS (one coalesced copy per block).
+    extern __shared__ double s_bins[];  // running maximum ends, then starts
+    const bool in_lds = ix.nb <= kQprepLdsBins;
+    if (in_lds) {
+        for (int k = threadIdx.x; k < ix.nb; k += blockDim.x) {
+            s_bins[k] = ix.bpend[k];
+            s_bins[ix.nb + k] = ix.bstart[k];
+        }
+        __syncthreads();
+    }
+    const double *bpend = in_lds ? s_bins : ix.bpend;
+    const double *bstart = in_lds ? s_bins + ix.nb : ix.bstart;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long novl = 0;
     if (i < b.nq) {
@@ -203,11 +218,11 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         // Candidate bins: j1 = first bin whose running maximum end exceeds
         // t0, j2 = last bin whose start is below t1 (spans must overlap with
         // positive length).
-        int j1 = first_greater(ix.bpend, ix.nb, s0);
+        int j1 = first_greater(bpend, ix.nb, s0);
         int lo = 0, hi = ix.nb;  // number of bins with start < t1
         while (lo < hi) {
             int mid = (lo + hi) >> 1;
-            if (ix.bstart[mid] < s1) lo = mid + 1; else hi = mid;
+            if (bstart[mid] < s1) lo = mid + 1; else hi = mid;
         }
         int j2 = lo - 1;
         bool any = ok && j1 <= j2;
@@ -409,7 +424,8 @@ hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, D
     hipLaunchKernelGGL(k_zero_batch, dim3(zgrid), dim3(blk), 0, st, b);
     if (b.nq == 0) TDS_LAUNCH_CHECK();
     const int qgrid = (b.nq + blk - 1) / blk;
-    hipLaunchKernelGGL(k_qprep, dim3(qgrid), dim3(blk), 0, st, q[0], q[1], q[2], q[3], q[4], q[5],
+    const size_t lds = ix.nb <= kQprepLdsBins ? (size_t)ix.nb * 2 * sizeof(double) : 0;
+    hipLaunchKernelGGL(k_qprep, dim3(qgrid), dim3(blk), lds, st, q[0], q[1], q[2], q[3], q[4], q[5],
                        q[6], q[7], d, b, ix);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanBlock), 0, st, b, ix);
     hipLaunchKernelGGL(k_scatter, dim3(qgrid), dim3(blk), 0, st, b);
@@ -511,29 +527,47 @@ __device__ __forceinline__ void append(bool flag, const R &rec, R *__restrict__ 
 }
 
 // Tile owning work unit u: the last t in [0, n) with off[t] <= u (tiles
-// without units share their successor's offset).
+// without units share their successor's offset; off[0] = 0 <= u). A 64-way
+// search: each round the lanes probe 64 evenly spaced offsets of [lo, hi) and
+// the last probe <= u becomes lo, so n tiles take ceil(log64 n) rounds.
 __device__ __forceinline__ int tile_of_unit(const long long *__restrict__ off, int n, long long u) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (off[mid] <= u) lo = mid + 1; else hi = mid;
+    const int lane = (int)lane_id();
+    int lo = 0, hi = n;  // off[lo] <= u, and u < off[hi] when hi < n
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + lane * step;
+        const unsigned long long m = __ballot(p < hi && off[p] <= u);  // bit 0 always set
+        const int l = 63 - __builtin_clzll(m);
+        lo += l * step;
+        hi = min(hi, lo + step);
     }
-    return lo - 1;
+    return lo;
 }
 
 // Conservative binary32 box test: do the entry's bounding box and the
 // query's box (widened by d + band) overlap on all three axes? Each bound
 // difference keeps its sign under rounding (a flush of a tiny difference to
 // zero can only let a pair through), so every overlapping pair passes.
-__device__ __forceinline__ bool box_overlap(const float4 &b, const float2 &bz, const QBox32 &q) {
-    const float m1 = fmaxf(fmaxf(b.x - q.xhi, q.xlo - b.y), b.z - q.yhi);
-    const float m2 = fmaxf(fmaxf(q.ylo - b.w, bz.x - q.zhi), q.zlo - bz.y);
+// Both boxes as (xlo, xhi, ylo, yhi) and (zlo, zhi).
+__device__ __forceinline__ bool box_overlap(const float4 &b, const float2 &bz, const float4 &q,
+                                            const float2 &qz) {
+    const float m1 = fmaxf(fmaxf(b.x - q.y, q.x - b.y), b.z - q.w);
+    const float m2 = fmaxf(fmaxf(q.z - b.w, bz.x - qz.y), qz.x - bz.y);
     return fmaxf(m1, m2) <= 0.0f;
 }
 
-struct QBox2 {
-    QBox32 a, b;
-};
+// Query boxes staged in LDS per wave: 64 at a time, one per lane.
+constexpr int kStage = 64;
+
+// Wave priority for the SIMD's instruction arbiter (0 lowest .. 3 highest).
+__device__ __forceinline__ void set_prio(int p) {
+    switch (p) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
 
 // Entries per lane: each wave holds 64 * EPT candidate entries of a chunk.
 #ifndef TDS_EPT32
@@ -552,9 +586,10 @@ __device__ __forceinline__ long long rfl64(long long v) {
 // one chunk of <= 64*EPT candidate entries of its tile) are numbered tile by
 // tile, query-fastest, and wave w of W resident waves takes the contiguous
 // range [w*U/W, (w+1)*U/W): every wave gets the same amount of work and
-// consecutive units of a wave share their chunk, so a wave loads each chunk
-// once. Lane l holds entries c0 + 64*j + l (slot j < EPT); the query records
-// are wave-uniform and come through the scalar cache.
+// consecutive units share their chunk, so a wave loads each chunk once. Lane l
+// holds entries c0 + 64*j + l (slot j < EPT); the query segment is
+// wave-uniform: binary64 records come through the scalar cache, binary32
+// boxes are staged in LDS.
 //
 // The kernel only selects pairs: in binary64 mode the pairs the pinned
 // decision calls hits, in binary32 mode the pairs that survive the box
@@ -570,14 +605,20 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                                                 Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
     const long long nwaves = (long long)gridDim.x * (BLOCK / 64);
-    const long long w =
-        (long long)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long total = rfl64((long long)ctr->n_units);
     const int ntiles = __builtin_amdgcn_readfirstlane((int)ctr->n_tiles);
-    long long u = (w * total) / nwaves;
-    const long long uend = ((w + 1) * total) / nwaves;
     unsigned long long ovl_acc = 0;
-    int t = u < uend ? tile_of_unit(unit_off, ntiles, u) : 0;
+    // progress-based wave priority (see below): one step down per pr_step units
+    int prio = 3, pr_step = 1, pr_next = 1;
+    auto progress = [&]() {
+        if (--pr_next == 0) {
+            pr_next = pr_step;
+            if (prio > 0) set_prio(--prio);
+        }
+    };
+    // Units [u, uend) of consecutive tiles.
+    auto run_range = [&](long long u, const long long uend) {
+    int t = tile_of_unit(unit_off, ntiles, u);
     while (u < uend) {
         const Tile tl = tiles[t];
         const long long base = unit_off[t];
@@ -620,6 +661,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     for (int qs = qb; qs < qe; ++qs) {
                         const QRec64 q = qn;
                         qn = rec[qs + 1];  // prefetch (the sorted arrays carry one spare slot)
+                        progress();
 #pragma unroll
                         for (int j = 0; j < EPT; ++j) {
                             if (!FULL && j >= nv) break;  // wave-uniform
@@ -652,7 +694,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         bz[j] = make_float2(INFINITY, -INFINITY);
                     }
                 }
-                auto test_query = [&](const QBox32 &qq, const int qs, auto full) {
+                auto test_query = [&](const float4 &qxy, const float2 &qz, const int qs, auto full) {
                     constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
                     bool pass[EPT];
                     bool any = false;
@@ -660,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     for (int j = 0; j < EPT; ++j) {
                         pass[j] = false;
                         if (FULL || j < nv) {  // wave-uniform: skip slots without entries
-                            pass[j] = box_overlap(bxy[j], bz[j], qq);
+                            pass[j] = box_overlap(bxy[j], bz[j], qxy, qz);
                             any |= pass[j];
                         }
                     }
@@ -680,16 +722,27 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         }
                     }
                 };
+                // The wave stages up to 64 query boxes in its LDS slice (one
+                // coalesced load, lane i takes box s0 + i), then walks them with
+                // broadcast LDS reads; the other waves of the SIMD cover their
+                // latency. LDS requests of one wave complete in order, so the
+                // slice is rewritten only after the previous walk has read it.
+                __shared__ float4 s_qxy[BLOCK / 64][kStage];
+                __shared__ float2 s_qz[BLOCK / 64][kStage];
+                const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
                 auto walk = [&](auto full) {
-                    // Two query boxes (64 B) per scalar load, the next pair
-                    // requested before the current pair is tested.
-                    QBox2 cur = *reinterpret_cast<const QBox2 *>(box + qb);
-                    for (int qs = qb; qs < qe; qs += 2) {
-                        // the sorted arrays carry spare slots past the end
-                        const QBox2 nxt = *reinterpret_cast<const QBox2 *>(box + qs + 2);
-                        test_query(cur.a, qs, full);
-                        if (qs + 1 < qe) test_query(cur.b, qs + 1, full);
-                        cur = nxt;
+                    for (int s0 = qb; s0 < qe; s0 += kStage) {
+                        const int ns = __builtin_amdgcn_readfirstlane(min(kStage, qe - s0));
+                        if (lane < ns) {
+                            const QBox32 bb = box[s0 + lane];
+                            s_qxy[wv][lane] = make_float4(bb.xlo, bb.xhi, bb.ylo, bb.yhi);
+                            s_qz[wv][lane] = make_float2(bb.zlo, bb.zhi);
+                        }
+#pragma unroll 2
+                        for (int j = 0; j < ns; ++j) {
+                            test_query(s_qxy[wv][j], s_qz[wv][j], s0 + j, full);
+                            progress();
+                        }
                     }
                 };
                 if (nv == EPT)
@@ -700,6 +753,20 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
         }
         ++t;
     }
+    };
+    // Even static split over the launched waves (every wave is resident from
+    // the start, see resident_blocks). The SIMD issues the oldest ready wave
+    // first, so without correction the first waves finish early and the last
+    // ones run nearly alone; each wave therefore lowers its priority by one
+    // step per quarter of its share done, keeping the waves of a SIMD at
+    // similar progress so they finish together.
+    const long long w =
+        (long long)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long u0 = (w * total) / nwaves, u1 = ((w + 1) * total) / nwaves;
+    pr_step = (int)max(1LL, min((u1 - u0) / 4, (long long)INT_MAX));
+    pr_next = pr_step;
+    set_prio(3);
+    if (u0 < u1) run_range(u0, u1);
     if (COUNT_OVL && lane == 0 && ovl_acc) atomicAdd(&ctr->overlap, ovl_acc);
 }
 
@@ -733,7 +800,11 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
     }
 }
 
-// Resident waves of a pair-kernel instantiation (grid of the persistent launch).
+// Grid of a persistent launch: the blocks that are resident at once. On
+// MI355X a launch sized by the occupancy query leaves one wave per SIMD (per
+// CU: 4 waves) without a slot, measured with per-wave start stamps: that many
+// blocks start only when others end and then run their share alone. So one
+// wave per SIMD less is launched than the query reports.
 template <class K>
 static int resident_blocks(K kernel, int block) {
     int dev = 0, cus = 256, per_cu = 0;
@@ -742,7 +813,10 @@ static int resident_blocks(K kernel, int block) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    return cus * per_cu;
+    const int wpb = block / 64;                 // waves per block
+    const int per_simd = per_cu * wpb / 4;      // waves per SIMD the query allows
+    const int fit = ((per_simd - 1) * 4) / wpb;  // blocks per CU with one wave per SIMD less
+    return cus * (fit < 1 ? 1 : fit);
 }
 
 template <int MODE, int BLOCK>
