@@ -42,11 +42,36 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 FP64_PEAK = 78.6e12
 # Algorithmic work per temporally overlapping pair:
 FP64_FLOPS_PER_PAIR = 49          # binary64 decision, FMA = 2
-FILTER_OPS_PER_PAIR = 6           # binary32 box test: 6 bound compares
+FILTER_OPS_PER_PAIR = 6           # binary32 cube test: 3 centre differences + 3 |.| - h per candidate pair
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_1405_7461_amd", "csrc", "tds_kernels.hip")
+
+
+def measured_traffic(summary: str):
+    """HBM bytes per launch of the pair kernel from a committed counter summary.
+
+    The summary (profiles/*.txt) records the FETCH_SIZE + WRITE_SIZE reading per
+    dispatch, already scaled by the copy-kernel calibration, together with the
+    SHA-256 of the kernel source it was taken on; a changed source gives None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    try:
+        fields = dict(line.split(":", 1) for line in open(path) if ":" in line)
+    except OSError:
+        return None
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256", "").strip() != src:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def overlap_count(db, q) -> int:
@@ -271,18 +296,24 @@ def main():
     if "fp32_refine" in results and "fp64" in results:
         assert results["fp32_refine"]["n_hit"] == results["fp64"]["n_hit"]
 
+    for name, r in results.items():  # each form against its own peak
+        if name == "fp32_refine":
+            r["roofline_frac"] = FILTER_OPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3) / VALU_LANE_OPS
+        else:
+            r["roofline_frac"] = FP64_FLOPS_PER_PAIR * n_ovl / (r["pair_ms"] / 1e3) / FP64_PEAK
     head_name = "fp32_refine" if "fp32_refine" in results else list(results)[0]
     head = results[head_name]
     if head_name == "fp32_refine":
-        ach = FILTER_OPS_PER_PAIR * n_ovl / (head["pair_ms"] / 1e3)
+        ach = FILTER_OPS_PER_PAIR * head["n_eval"] / (head["pair_ms"] / 1e3)
         roof = dict(bound="alu", achieved=ach / 1e12, peak=VALU_LANE_OPS / 1e12, unit="TFLOP/s",
-                    frac=ach / VALU_LANE_OPS, traffic=None,
-                    kernel="k_pair<fp32_refine>", per_unit=f"{FILTER_OPS_PER_PAIR} binary32 ops per overlapping pair",
-                    units_per_launch=n_ovl, launch_ms=head["pair_ms"])
+                    frac=ach / VALU_LANE_OPS, traffic=measured_traffic("k_pair_fp32_c2_hbm.txt"),
+                    kernel="k_pair<fp32_refine>", per_unit=f"{FILTER_OPS_PER_PAIR} binary32 ops per candidate pair",
+                    units_per_launch=head["n_eval"], launch_ms=head["pair_ms"])
     else:
         ach = FP64_FLOPS_PER_PAIR * n_ovl / (head["pair_ms"] / 1e3)
         roof = dict(bound="alu", achieved=ach / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
-                    frac=ach / FP64_PEAK, traffic=None, kernel="k_pair<fp64>",
+                    frac=ach / FP64_PEAK, traffic=measured_traffic("k_pair_fp64_c2_hbm.txt"),
+                    kernel="k_pair<fp64>",
                     per_unit=f"{FP64_FLOPS_PER_PAIR} binary64 flops per overlapping pair",
                     units_per_launch=n_ovl, launch_ms=head["pair_ms"])
     line = {

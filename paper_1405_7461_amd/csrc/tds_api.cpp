@@ -118,7 +118,7 @@ struct tds_index {
     int32_t m = 0;
     double t_first = 0, t_last = 0, width = 1;
     std::vector<tds_bin> bins;
-    DBuf t0, t1, x0, y0, z0, vx, vy, vz, boxxy, boxz, orig, traj, t1s;
+    DBuf t0, t1, x0, y0, z0, vx, vy, vz, ecen, ehalf, orig, traj, t1s;
     DBuf bstart, bpend, bfirst, blast;
     DevIndex dev{};
     int64_t device_bytes = 0;
@@ -268,8 +268,8 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
                     &ix->traj, &ix->t1s})
         IX_TRY(b->ensure(n1 * 8));
-    IX_TRY(ix->boxxy.ensure(n1 * 16));
-    IX_TRY(ix->boxz.ensure(n1 * 8));
+    IX_TRY(ix->ecen.ensure(n1 * 16));
+    IX_TRY(ix->ehalf.ensure(n1 * 8));
     IX_TRY(ix->orig.ensure(n1 * 4));
     const size_t nb1 = (size_t)std::max<int64_t>(nb, 1);
     IX_TRY(ix->bstart.ensure(nb1 * 8));
@@ -313,7 +313,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
         IX_TRY(launch_ingest(rawp, n, dperm.as<int32_t>(), traj_dev, ix->t0.as<double>(),
                              ix->t1.as<double>(), ix->x0.as<double>(), ix->y0.as<double>(),
                              ix->z0.as<double>(), ix->vx.as<double>(), ix->vy.as<double>(),
-                             ix->vz.as<double>(), ix->boxxy.as<float4>(), ix->boxz.as<float2>(),
+                             ix->vz.as<double>(), ix->ecen.as<float4>(), ix->ehalf.as<float2>(),
                              ix->orig.as<int32_t>(), ix->traj.as<int64_t>(), st));
         IX_TRY(hipMemcpyAsync(ix->t1s.p, t1s.data(), n * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->bstart.p, bs.data(), nb * 8, hipMemcpyHostToDevice, st));
@@ -341,8 +341,8 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.vx = ix->vx.as<double>();
     d.vy = ix->vy.as<double>();
     d.vz = ix->vz.as<double>();
-    d.boxxy = ix->boxxy.as<float4>();
-    d.boxz = ix->boxz.as<float2>();
+    d.ecen = ix->ecen.as<float4>();
+    d.ehalf = ix->ehalf.as<float2>();
     d.orig = ix->orig.as<int32_t>();
     d.traj = ix->traj.as<int64_t>();
     d.t1s = ix->t1s.as<double>();
@@ -385,7 +385,7 @@ int tds_index_bins(const tds_index *ix, tds_bin *out, int64_t cap, int64_t *n_ou
 void tds_index_destroy(tds_index *ix) {
     if (!ix) return;
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
-                    &ix->boxxy, &ix->boxz, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
+                    &ix->ecen, &ix->ehalf, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
                     &ix->bfirst, &ix->blast})
         b->release();
     delete ix;
@@ -435,8 +435,8 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
         size_t n = (size_t)c, n1 = n + 1;
         HIP_TRY(q->rec.ensure(n * sizeof(QRec64)));
         HIP_TRY(q->rec_s.ensure(n1 * sizeof(QRec64)));
-        HIP_TRY(q->box.ensure(n * sizeof(QBox32)));
-        HIP_TRY(q->box_s.ensure((n + 4) * sizeof(QBox32)));  // read-ahead slots
+        HIP_TRY(q->box.ensure(n * sizeof(QCube32)));
+        HIP_TRY(q->box_s.ensure(n1 * sizeof(QCube32)));
         for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->key, &q->perm})
             HIP_TRY(b->ensure(n * 4));
         HIP_TRY(q->tiles.ensure(n1 * sizeof(Tile)));
@@ -553,8 +553,8 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.count_overlap = (o.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0;
     b.rec = q->rec.as<QRec64>();
     b.rec_s = q->rec_s.as<QRec64>();
-    b.box = q->box.as<QBox32>();
-    b.box_s = q->box_s.as<QBox32>();
+    b.box = q->box.as<QCube32>();
+    b.box_s = q->box_s.as<QCube32>();
     b.first = q->first.as<int32_t>();
     b.last = q->last.as<int32_t>();
     b.first_s = q->first_s.as<int32_t>();

@@ -17,11 +17,11 @@ struct QRec64 {
     double pad;
 };
 
-// Conservative binary32 box of a query segment: spatial bounding box widened
-// by d + band and rounded outward, plus its span rounded outward (32 bytes).
-struct alignas(32) QBox32 {
-    float xlo, xhi, ylo, yhi, zlo, zhi;
-    float t0, t1;
+// Conservative binary32 region of a query segment: the cube of half-width r
+// about (cx, cy, cz) that contains its bounding box widened by d + band on
+// every axis, with the slack the binary32 test needs (16 bytes).
+struct alignas(16) QCube32 {
+    float cx, cy, cz, r;
 };
 
 // A tile: sorted query segments [q0, q0 + nq) against entries [e0, e0 + ne).
@@ -74,8 +74,8 @@ struct DevIndex {
     int32_t m;   // bins as requested
     double t_first, width;
     const double *t0, *t1, *x0, *y0, *z0, *vx, *vy, *vz;
-    const float4 *boxxy;  // (xlo, xhi, ylo, yhi), rounded outward
-    const float2 *boxz;   // (zlo, zhi), rounded outward
+    const float4 *ecen;   // entry box as (cx, cy, cz, hx): centre, x half-width
+    const float2 *ehalf;  // (hy, hz); [c - h, c + h] contains the segment on each axis
     const int32_t *orig;  // caller index of each sorted entry
     const int64_t *traj;  // trajectory id of each sorted entry
     const double *t1s;    // t_end, sorted independently (overlap counts)
@@ -101,7 +101,7 @@ struct DevBatch {
     int32_t count_overlap;      // exact overlap count in the query preparation
     int32_t pad;
     QRec64 *rec, *rec_s;  // caller order, sorted order (+1 padding slot)
-    QBox32 *box, *box_s;
+    QCube32 *box, *box_s;
     int32_t *first, *last;      // caller order candidate range (last < first: empty)
     int32_t *first_s, *last_s;  // sorted order
     int32_t *key;               // caller order bucket (-1: no candidates)
@@ -119,8 +119,8 @@ enum : int { kTilePeriodic = 0, kTileRange = 1 };
 // Launchers (tds_kernels.hip). All enqueue on `st`, return hipError_t.
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
-                         double *z0, double *vx, double *vy, double *vz, float4 *boxxy,
-                         float2 *boxz, int32_t *orig, int64_t *traj, hipStream_t st);
+                         double *z0, double *vx, double *vy, double *vz, float4 *ecen,
+                         float2 *ehalf, int32_t *orig, int64_t *traj, hipStream_t st);
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
                           hipStream_t st);
 // grid <= 0: one workgroup per resident slot (persistent launch); the grid

@@ -44,6 +44,17 @@ __device__ __forceinline__ float f32_up(double x) {
     return ((double)f < x) ? nextafterf(f, INFINITY) : f;
 }
 
+// Interval [lo, hi] as a binary32 centre c and half-width h with
+// [c - h, c + h] containing it (h rounded up from the binary64 difference).
+__device__ __forceinline__ void centre_half(double lo, double hi, float &c, float &h) {
+    c = (float)(0.5 * lo + 0.5 * hi);
+    const double cd = (double)c;
+    h = f32_up(dmx(hi - cd, cd - lo));
+}
+// Coordinates (and query half-widths) up to this magnitude take part in the
+// binary32 test; beyond it a region is made unbounded so that it passes.
+constexpr double kCubeLimit = 0x1p100;
+
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -60,8 +71,8 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
                          const double *__restrict__ rz1, const double *__restrict__ rt1,
                          int64_t n, const int32_t *__restrict__ perm,
                          const int64_t *__restrict__ traj_raw, double *t0, double *t1, double *x0,
-                         double *y0, double *z0, double *vx, double *vy, double *vz, float4 *boxxy,
-                         float2 *boxz, int32_t *orig, int64_t *traj) {
+                         double *y0, double *z0, double *vx, double *vy, double *vz, float4 *ecen,
+                         float2 *ehalf, int32_t *orig, int64_t *traj) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int32_t i = perm[p];
@@ -76,23 +87,32 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
     vx[p] = (a1 - a0) / dt;
     vy[p] = (b1 - b0) / dt;
     vz[p] = (c1 - c0) / dt;
-    boxxy[p] = make_float4(f32_down(dmn(a0, a1)), f32_up(dmx(a0, a1)), f32_down(dmn(b0, b1)),
-                           f32_up(dmx(b0, b1)));
-    boxz[p] = make_float2(f32_down(dmn(c0, c1)), f32_up(dmx(c0, c1)));
+    float cx, cy, cz, hx, hy, hz;
+    if (dmx(dmx(dmx(fabs(a0), fabs(a1)), dmx(fabs(b0), fabs(b1))), dmx(fabs(c0), fabs(c1))) <=
+        kCubeLimit) {
+        centre_half(dmn(a0, a1), dmx(a0, a1), cx, hx);
+        centre_half(dmn(b0, b1), dmx(b0, b1), cy, hy);
+        centre_half(dmn(c0, c1), dmx(c0, c1), cz, hz);
+    } else {  // beyond the binary32 test's range: an unbounded box passes every query
+        cx = cy = cz = 0.0f;
+        hx = hy = hz = INFINITY;
+    }
+    ecen[p] = make_float4(cx, cy, cz, hx);
+    ehalf[p] = make_float2(hy, hz);
     orig[p] = i;
     traj[p] = traj_raw ? traj_raw[i] : (int64_t)i;
 }
 
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
-                         double *z0, double *vx, double *vy, double *vz, float4 *boxxy,
-                         float2 *boxz, int32_t *orig, int64_t *traj, hipStream_t st) {
+                         double *z0, double *vx, double *vy, double *vz, float4 *ecen,
+                         float2 *ehalf, int32_t *orig, int64_t *traj, hipStream_t st) {
     if (n == 0) return hipSuccess;
     int blk = 256;
     int64_t grid = (n + blk - 1) / blk;
     hipLaunchKernelGGL(k_ingest, dim3((unsigned)grid), dim3(blk), 0, st, raw[0], raw[1], raw[2],
                        raw[3], raw[4], raw[5], raw[6], raw[7], n, perm_sorted, traj_raw, t0, t1, x0,
-                       y0, z0, vx, vy, vz, boxxy, boxz, orig, traj);
+                       y0, z0, vx, vy, vz, ecen, ehalf, orig, traj);
     TDS_LAUNCH_CHECK();
 }
 
@@ -204,15 +224,23 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         double mag = dmx(dmx(fabs(a0), fabs(a1)), dmx(dmx(fabs(b0), fabs(b1)), dmx(fabs(c0), fabs(c1))));
         double w = d + ix.band_rel * (d + ext + ix.ext_max) +
                    ix.band_abs * (1.0 + d + mag + ext + ix.mag_max + ix.ext_max);
-        QBox32 bx;
-        bx.xlo = f32_down(dmn(a0, a1) - w);
-        bx.xhi = f32_up(dmx(a0, a1) + w);
-        bx.ylo = f32_down(dmn(b0, b1) - w);
-        bx.yhi = f32_up(dmx(b0, b1) + w);
-        bx.zlo = f32_down(dmn(c0, c1) - w);
-        bx.zhi = f32_up(dmx(c0, c1) + w);
-        bx.t0 = f32_down(s0);
-        bx.t1 = f32_up(s1);
+        // The widened box as a cube: centre C and the largest half-width r.
+        // The binary32 test computes |c - C| - h per axis; its rounding stays
+        // below 2^-22 (r + h + |c - C|) for pairs near the threshold, covered
+        // by the 2^-20 (r + ext_max) slack (entry half-widths are at most
+        // ext_max / 2).
+        QCube32 bx;
+        if (mag + w <= kCubeLimit) {
+            float hx, hy, hz;
+            centre_half(dmn(a0, a1) - w, dmx(a0, a1) + w, bx.cx, hx);
+            centre_half(dmn(b0, b1) - w, dmx(b0, b1) + w, bx.cy, hy);
+            centre_half(dmn(c0, c1) - w, dmx(c0, c1) + w, bx.cz, hz);
+            const double r = dmx(dmx((double)hx, (double)hy), (double)hz);
+            bx.r = f32_up(r + 0x1p-20 * (r + ix.ext_max));
+        } else {  // beyond the binary32 test's range: pass every entry
+            bx.cx = bx.cy = bx.cz = 0.0f;
+            bx.r = INFINITY;
+        }
         b.box[i] = bx;
 
         // Candidate bins: j1 = first bin whose running maximum end exceeds
@@ -544,16 +572,13 @@ __device__ __forceinline__ int tile_of_unit(const long long *__restrict__ off, i
     return lo;
 }
 
-// Conservative binary32 box test: do the entry's bounding box and the
-// query's box (widened by d + band) overlap on all three axes? Each bound
-// difference keeps its sign under rounding (a flush of a tiny difference to
-// zero can only let a pair through), so every overlapping pair passes.
-// Both boxes as (xlo, xhi, ylo, yhi) and (zlo, zhi).
-__device__ __forceinline__ bool box_overlap(const float4 &b, const float2 &bz, const float4 &q,
-                                            const float2 &qz) {
-    const float m1 = fmaxf(fmaxf(b.x - q.y, q.x - b.y), b.z - q.w);
-    const float m2 = fmaxf(fmaxf(q.z - b.w, bz.x - qz.y), qz.x - bz.y);
-    return fmaxf(m1, m2) <= 0.0f;
+// Conservative binary32 test: do the entry's box and the query's cube (its
+// box widened by d + band, with rounding slack) overlap on every axis?
+// Largest per-axis gap |c - C| - h between an entry box (centre c, half-
+// widths h) and a query centre C: the pair passes when it is <= the query's
+// r. NaN (an empty slot) never passes.
+__device__ __forceinline__ float cube_gap(const float4 &c, const float2 &h, const float4 &q) {
+    return fmaxf(fmaxf(fabsf(c.x - q.x) - c.w, fabsf(c.y - q.y) - h.x), fabsf(c.z - q.z) - h.y);
 }
 
 // Query boxes staged in LDS per wave: 64 at a time, one per lane.
@@ -598,7 +623,7 @@ __device__ __forceinline__ long long rfl64(long long v) {
 // registers weigh on this loop.
 template <int MODE, int BLOCK, int EPT, bool COUNT_OVL>
 __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
-                                                const QBox32 *__restrict__ box,
+                                                const QCube32 *__restrict__ box,
                                                 const Tile *__restrict__ tiles,
                                                 const long long *__restrict__ unit_off, DevIndex ix,
                                                 Cand *__restrict__ cand, unsigned long long cap,
@@ -678,38 +703,38 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 else
                     walk(std::false_type{});
             } else {
-                // Conservative binary32 filter: the entry's bounding box against
-                // the query's box widened by d + band; outward rounding on both
-                // sides keeps every binary64 hit. Time is left to the refine.
-                float4 bxy[EPT];
-                float2 bz[EPT];
+                // Conservative binary32 filter: the entry's box against the
+                // query's cube; time is left to the refine.
+                float4 ec[EPT];
+                float2 eh[EPT];
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) {
                     const int e = wb + j * 64 + lane;
                     if (e < we) {
-                        bxy[j] = ix.boxxy[e];
-                        bz[j] = ix.boxz[e];
-                    } else {  // an empty box never passes
-                        bxy[j] = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-                        bz[j] = make_float2(INFINITY, -INFINITY);
+                        ec[j] = ix.ecen[e];
+                        eh[j] = ix.ehalf[e];
+                    } else {  // an empty slot (NaN) never passes
+                        ec[j] = make_float4(NAN, NAN, NAN, NAN);
+                        eh[j] = make_float2(NAN, NAN);
                     }
                 }
-                auto test_query = [&](const float4 &qxy, const float2 &qz, const int qs, auto full) {
+                auto test_query = [&](const float4 &qc, const int qs, auto full) {
                     constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
-                    bool pass[EPT];
-                    bool any = false;
+                    float gap[EPT];
+                    gap[0] = cube_gap(ec[0], eh[0], qc);  // slot 0 always holds entries
+                    float gmin = gap[0];
 #pragma unroll
-                    for (int j = 0; j < EPT; ++j) {
-                        pass[j] = false;
+                    for (int j = 1; j < EPT; ++j) {
+                        gap[j] = NAN;
                         if (FULL || j < nv) {  // wave-uniform: skip slots without entries
-                            pass[j] = box_overlap(bxy[j], bz[j], qxy, qz);
-                            any |= pass[j];
+                            gap[j] = cube_gap(ec[j], eh[j], qc);
+                            gmin = fminf(gmin, gap[j]);
                         }
                     }
-                    if (__builtin_expect(__ballot(any) != 0ull, 0)) {  // rare: a box overlaps
+                    if (__builtin_expect(__ballot(gmin <= qc.w) != 0ull, 0)) {  // rare
 #pragma unroll
                         for (int j = 0; j < EPT; ++j)
-                            append(pass[j], Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)},
+                            append(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)},
                                    cand, cap, &ctr->cand);
                     }
                     if (COUNT_OVL) {
@@ -722,25 +747,23 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         }
                     }
                 };
-                // The wave stages up to 64 query boxes in its LDS slice (one
-                // coalesced load, lane i takes box s0 + i), then walks them with
+                // The wave stages up to 64 query cubes in its LDS slice (one
+                // coalesced load, lane i takes cube s0 + i), then walks them with
                 // broadcast LDS reads; the other waves of the SIMD cover their
                 // latency. LDS requests of one wave complete in order, so the
                 // slice is rewritten only after the previous walk has read it.
-                __shared__ float4 s_qxy[BLOCK / 64][kStage];
-                __shared__ float2 s_qz[BLOCK / 64][kStage];
+                __shared__ float4 s_q[BLOCK / 64][kStage];
                 const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
                 auto walk = [&](auto full) {
                     for (int s0 = qb; s0 < qe; s0 += kStage) {
                         const int ns = __builtin_amdgcn_readfirstlane(min(kStage, qe - s0));
                         if (lane < ns) {
-                            const QBox32 bb = box[s0 + lane];
-                            s_qxy[wv][lane] = make_float4(bb.xlo, bb.xhi, bb.ylo, bb.yhi);
-                            s_qz[wv][lane] = make_float2(bb.zlo, bb.zhi);
+                            const QCube32 c = box[s0 + lane];
+                            s_q[wv][lane] = make_float4(c.cx, c.cy, c.cz, c.r);
                         }
 #pragma unroll 2
                         for (int j = 0; j < ns; ++j) {
-                            test_query(s_qxy[wv][j], s_qz[wv][j], s0 + j, full);
+                            test_query(s_q[wv][j], s0 + j, full);
                             progress();
                         }
                     }
