@@ -131,8 +131,10 @@ struct tds_query {
     int32_t cap_buckets = 0;  // bucket slots allocated
     DBuf rec, box, rec_s, box_s, first, last, first_s, last_s, key, perm;
     DBuf bcount, bj2, bcursor, bq_off, tiles, units, unit_off, ctr;
-    DBuf qstage, cand, hits, out_stage;
-    unsigned long long cap_cand = 0, cap_hits = 0;
+    DBuf qstage, cand, hits, slab_n, slab_h, hit_off, wave_ovl, out_stage;
+    Slabs sl{};                    // slab view of the buffers above
+    long long nslabs_alloc = 0;    // slabs the cand / hits buffers hold
+    int32_t nwaves_alloc = 0;      // wave slabs slab_n / wave_ovl hold
     Counters *host_ctr = nullptr;  // pinned
     hipStream_t stream = nullptr;
     DevBatch b{};
@@ -419,7 +421,7 @@ void tds_query_destroy(tds_query *q) {
     for (DBuf *b : {&q->rec, &q->box, &q->rec_s, &q->box_s, &q->first, &q->last, &q->first_s,
                     &q->last_s, &q->key, &q->perm, &q->bcount, &q->bj2, &q->bcursor, &q->bq_off,
                     &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
-                    &q->hits, &q->out_stage})
+                    &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage})
         b->release();
     if (q->host_ctr) (void)hipHostFree(q->host_ctr);
     for (auto &ev : q->ev)
@@ -453,21 +455,51 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
     return TDS_OK;
 }
 
-// Pair kernel (selects pairs) then refine kernel (turns them into hits), with
-// HIP events around each when timing is on. pair = 0 runs the refine only.
-static int launch_search(tds_query *q, bool pair) {
-    const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
-    if (timing) HIP_TRY(hipEventRecord(q->ev[1], q->stream));
-    if (pair) {
-        int used = 0;
-        HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->opts.grid,
-                            (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0, q->cand.as<Cand>(),
-                            q->cap_cand, q->stream, &used));
-        q->grid = used;
+// Slab buffers for a pair launch of `nwaves` waves with room for `spill`
+// selections beyond the wave slabs (grown, never shrunk).
+static int ensure_slabs(tds_query *q, int32_t nwaves, unsigned long long spill) {
+    const long long want = (long long)nwaves + 1 + (long long)((spill + kSlab - 1) / kSlab);
+    if (want > q->nslabs_alloc) {
+        const long long n = std::max<long long>(want, q->nslabs_alloc + q->nslabs_alloc / 2);
+        HIP_TRY(q->cand.ensure((size_t)n * kSlab * sizeof(Cand)));
+        HIP_TRY(q->hits.ensure((size_t)n * kSlab * sizeof(Hit24)));
+        HIP_TRY(q->slab_h.ensure((size_t)n * sizeof(int32_t)));
+        HIP_TRY(q->hit_off.ensure((size_t)(n + 1) * sizeof(long long)));
+        q->nslabs_alloc = n;
     }
+    if (nwaves > q->nwaves_alloc) {
+        HIP_TRY(q->slab_n.ensure((size_t)nwaves * sizeof(int32_t)));
+        HIP_TRY(q->wave_ovl.ensure((size_t)nwaves * sizeof(unsigned long long)));
+        q->nwaves_alloc = nwaves;
+    }
+    Slabs &sl = q->sl;
+    sl.cand = q->cand.as<Cand>();
+    sl.hits = q->hits.as<Hit24>();
+    sl.slab_n = q->slab_n.as<int32_t>();
+    sl.slab_h = q->slab_h.as<int32_t>();
+    sl.hit_off = q->hit_off.as<long long>();
+    sl.wave_ovl = q->wave_ovl.as<unsigned long long>();
+    sl.nwaves = nwaves;
+    sl.pad = 0;
+    sl.nslabs = q->nslabs_alloc;
+    return TDS_OK;
+}
+
+static unsigned long long spill_capacity(const Slabs &sl) {
+    return (unsigned long long)(sl.nslabs - sl.nwaves) * kSlab;
+}
+
+// Pair kernel (selects pairs), then refine (turns them into hits) and the hit
+// scan, with HIP events around the pair kernel and the refine when timing is
+// on; the counters are copied back on the same stream.
+static int launch_search(tds_query *q) {
+    const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
+    const int kovl = (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
+    if (timing) HIP_TRY(hipEventRecord(q->ev[1], q->stream));
+    HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->opts.grid, kovl, q->sl,
+                        q->stream));
     if (timing) HIP_TRY(hipEventRecord(q->ev[2], q->stream));
-    HIP_TRY(launch_refine(q->b, q->ix->dev, q->cand.as<Cand>(), q->cap_cand, q->hits.as<Hit24>(),
-                          q->cap_hits, q->stream));
+    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream));
     if (timing) HIP_TRY(hipEventRecord(q->ev[3], q->stream));
     HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
                            q->stream));
@@ -516,16 +548,15 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     q->block = o.block_size;
     int rc = ensure_capacity(q, std::max<int32_t>(nq, 1), nbuckets);
     if (rc) return rc;
-    unsigned long long want = o.capacity > 0 ? (unsigned long long)o.capacity : (1ull << 20);
-    if (q->cap_hits < want || !q->hits.p) {
-        HIP_TRY(q->hits.ensure(want * sizeof(Hit24)));
-        q->cap_hits = q->hits.bytes / sizeof(Hit24);
-    }
-    unsigned long long want_cand = std::max<unsigned long long>(want, 1ull << 22);
-    if (q->cap_cand < want_cand || !q->cand.p) {
-        HIP_TRY(q->cand.ensure(want_cand * sizeof(Cand)));
-        q->cap_cand = q->cand.bytes / sizeof(Cand);
-    }
+    const int kovl = (o.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
+    const int grid = pair_grid(o.mode, o.block_size, o.grid, kovl);
+    if (grid < 1 || (long long)grid * (o.block_size / 64) > INT32_MAX / kSlab)
+        return fail(TDS_EINVAL, "tds_query_batch: grid %d not supported", grid);
+    q->grid = grid;
+    // capacity: selections beyond the per-wave slabs to make room for
+    const unsigned long long spill = o.capacity > 0 ? (unsigned long long)o.capacity : (1ull << 20);
+    rc = ensure_slabs(q, grid * (o.block_size / 64), spill);
+    if (rc) return rc;
 
     const double *qin[8];
     const double *din = d;
@@ -573,7 +604,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
     if (timing) HIP_TRY(hipEventRecord(q->ev[0], st));
     HIP_TRY(launch_prepare(qin, din, b, ix->dev, st));
-    rc = launch_search(q, true);
+    rc = launch_search(q);
     if (rc) return rc;
     q->pending = true;
     q->fetched = false;
@@ -597,31 +628,22 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
             return fail(TDS_EINVAL, "tds_fetch_results: the batch holds an invalid query "
                                     "segment (non-finite value, t_end <= t_start, or d < 0)");
         }
-        // Overflow (Sec. 5: re-attempt with more memory): a full selected-pair
-        // list re-runs both kernels, a full hit buffer only the refine.
+        // Overflow (Sec. 5: re-attempt with more memory): selections beyond
+        // the slabs were counted, not stored; grow and run the search again.
         int retries = 0;
-        while (c.cand > q->cap_cand || c.hits > q->cap_hits) {
+        while (c.spill > spill_capacity(q->sl)) {
             if (retries >= q->opts.max_retries) {
                 q->pending = false;
                 return fail(TDS_EOVERFLOW,
-                            "tds_fetch_results: %llu selected pairs / %llu hits exceed capacity "
-                            "%llu / %llu",
-                            c.cand, c.hits, q->cap_cand, q->cap_hits);
+                            "tds_fetch_results: %llu selections beyond the wave slabs exceed "
+                            "the capacity %llu",
+                            c.spill, spill_capacity(q->sl));
             }
             ++retries;
-            const bool again = c.cand > q->cap_cand;
-            if (again) {
-                unsigned long long need = c.cand + c.cand / 4 + 1024;
-                HIP_TRY(q->cand.ensure(need * sizeof(Cand)));
-                q->cap_cand = q->cand.bytes / sizeof(Cand);
-            }
-            if (c.hits > q->cap_hits) {
-                unsigned long long need = c.hits + c.hits / 4 + 1024;
-                HIP_TRY(q->hits.ensure(need * sizeof(Hit24)));
-                q->cap_hits = q->hits.bytes / sizeof(Hit24);
-            }
-            HIP_TRY(launch_reset_counters(q->b.ctr, again ? 1 : 0, st));
-            int rc = launch_search(q, again);
+            int rc = ensure_slabs(q, q->sl.nwaves, c.spill + c.spill / 4 + 1024);
+            if (rc) return rc;
+            HIP_TRY(launch_reset_counters(q->b.ctr, 1, st));
+            rc = launch_search(q);
             if (rc) return rc;
             HIP_TRY(hipStreamSynchronize(st));
             c = *q->host_ctr;
@@ -651,10 +673,10 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
         bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
         if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
         if (out_mem == TDS_MEM_DEVICE) {
-            HIP_TRY(launch_translate(q->hits.as<Hit24>(), m, q->b.perm, q->ix->dev, out, st));
+            HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, out, st));
         } else {
             HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
-            HIP_TRY(launch_translate(q->hits.as<Hit24>(), m, q->b.perm, q->ix->dev, q->out_stage.p, st));
+            HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, q->out_stage.p, st));
             HIP_TRY(hipMemcpyAsync(out, q->out_stage.p, (size_t)m * sizeof(tds_hit),
                                    hipMemcpyDeviceToHost, st));
         }

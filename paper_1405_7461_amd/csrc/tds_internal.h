@@ -53,6 +53,25 @@ struct Hit24 {
     double ta, tb;
 };
 
+// Selected pairs and hits live in slabs of kSlab records. Slab w < nwaves
+// belongs to wave w of the pair launch, which fills it without atomics; a
+// wave whose next selections do not fit its slab appends them to the shared
+// spill slabs after the wave slabs (one atomic per append). Hit slab s holds
+// the hits among selected-pair slab s, and k_hit_scan's offsets give the
+// position of each slab's hits in the dense output.
+constexpr int kSlab = 64;
+struct Slabs {
+    Cand *cand;                    // nslabs * kSlab
+    Hit24 *hits;                   // nslabs * kSlab
+    int32_t *slab_n;               // selected pairs in each wave slab [nwaves]
+    int32_t *slab_h;               // hits in each slab [nslabs]
+    long long *hit_off;            // exclusive scan of slab_h [nslabs + 1]
+    unsigned long long *wave_ovl;  // overlapping pairs counted by each wave [nwaves]
+    int32_t nwaves;                // waves of the pair launch (= wave slabs)
+    int32_t pad;
+    long long nslabs;              // slabs allocated (> nwaves)
+};
+
 // Device counters of one batch (zeroed at the start of the batch).
 struct Counters {
     unsigned long long hits;
@@ -65,6 +84,8 @@ struct Counters {
     unsigned int n_tiles;
     unsigned int n_sorted;       // query segments placed in tiles
     unsigned int pad;
+    unsigned long long spill;    // selections appended to the spill slabs (may exceed them)
+    unsigned long long n_slabs;  // slabs in use after the refine
 };
 
 // Index arrays in device memory (sorted by t_start).
@@ -123,14 +144,16 @@ hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *per
                          float2 *ehalf, int32_t *orig, int64_t *traj, hipStream_t st);
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
                           hipStream_t st);
-// grid <= 0: one workgroup per resident slot (persistent launch); the grid
-// actually launched is written to *grid_used.
+// Workgroups of the pair launch: `grid` when > 0, else one per resident slot
+// (persistent launch). Slabs.nwaves must be pair_grid(...) * block / 64.
+int pair_grid(int mode, int block, int grid, int kernel_overlap);
 hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int kernel_overlap,
-                       Cand *cand, unsigned long long cap, hipStream_t st, int *grid_used);
-hipError_t launch_refine(DevBatch b, DevIndex ix, const Cand *cand, unsigned long long cand_cap,
-                         Hit24 *out, unsigned long long cap, hipStream_t st);
-hipError_t launch_translate(const Hit24 *in, int64_t n, const int32_t *perm, DevIndex ix,
-                            void *out_hits, hipStream_t st);
+                       Slabs sl, hipStream_t st);
+// Refine the selected pairs into hit slabs, then scan the hit counts.
+hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st);
+// Dense caller-index records of the first n hits.
+hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
+                            DevIndex ix, void *out_hits, hipStream_t st);
 hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
 int chunk_for(int mode, int block);
 int nbuckets_for(int tiling, int nb, int m);

@@ -533,27 +533,6 @@ __device__ __forceinline__ void interval64(const Pair64 &p, double *ta, double *
     *tb = xb;
 }
 
-// Wave-aggregated append: one atomic per wave, lanes place their records by
-// their rank among the wave's flagged lanes. Records past `cap` are counted
-// but not stored (the host re-runs with a larger buffer).
-template <class R>
-__device__ __forceinline__ void append(bool flag, const R &rec, R *__restrict__ buf,
-                                       unsigned long long cap, unsigned long long *counter) {
-    const unsigned long long m = __ballot(flag);
-    if (m == 0ull) return;
-    const unsigned lane = lane_id();
-    const int leader = __ffsll((long long)m) - 1;
-    unsigned long long base = 0;
-    if ((int)lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader);
-    if (flag) {
-        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        const unsigned long long pos = base + rank;
-        if (pos < cap) buf[pos] = rec;
-    }
-}
-
 // Tile owning work unit u: the last t in [0, n) with off[t] <= u (tiles
 // without units share their successor's offset; off[0] = 0 <= u). A 64-way
 // search: each round the lanes probe 64 evenly spaced offsets of [lo, hi) and
@@ -626,13 +605,37 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                                                 const QCube32 *__restrict__ box,
                                                 const Tile *__restrict__ tiles,
                                                 const long long *__restrict__ unit_off, DevIndex ix,
-                                                Cand *__restrict__ cand, unsigned long long cap,
-                                                Counters *__restrict__ ctr) {
+                                                Slabs sl, Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
     const long long nwaves = (long long)gridDim.x * (BLOCK / 64);
+    const long long w =
+        (long long)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long total = rfl64((long long)ctr->n_units);
     const int ntiles = __builtin_amdgcn_readfirstlane((int)ctr->n_tiles);
     unsigned long long ovl_acc = 0;
+    // Selections go to this wave's slab while they fit, then to the spill
+    // slabs (one atomic per append there).
+    const long long cap = sl.nslabs * kSlab;
+    int n_own = w < sl.nwaves ? 0 : kSlab;  // waves beyond the slabs spill (not launched so)
+    auto select = [&](bool flag, const Cand &rec) {
+        const unsigned long long m = __ballot(flag);
+        if (m == 0ull) return;
+        const int cnt = __popcll(m);
+        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        long long pos;
+        if (n_own + cnt <= kSlab) {
+            pos = w * kSlab + n_own + rank;
+            n_own += cnt;
+        } else {
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&ctr->spill, (unsigned long long)cnt);
+            base = __shfl(base, leader);
+            pos = (long long)sl.nwaves * kSlab + (long long)(base + rank);
+        }
+        if (flag && pos < cap) sl.cand[pos] = rec;
+    };
     // progress-based wave priority (see below): one step down per pr_step units
     int prio = 3, pr_step = 1, pr_next = 1;
     auto progress = [&]() {
@@ -693,8 +696,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             const Pair64 p = decide64(q, et0[j], et1[j], ex0[j], ey0[j], ez0[j],
                                                       evx[j], evy[j], evz[j]);
                             if (COUNT_OVL) ovl_acc += __popcll(__ballot(p.tlo < p.thi));
-                            append(p.hit, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)}, cand,
-                                   cap, &ctr->cand);
+                            select(p.hit, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
                         }
                     }
                 };
@@ -734,8 +736,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     if (__builtin_expect(__ballot(gmin <= qc.w) != 0ull, 0)) {  // rare
 #pragma unroll
                         for (int j = 0; j < EPT; ++j)
-                            append(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)},
-                                   cand, cap, &ctr->cand);
+                            select(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
                     }
                     if (COUNT_OVL) {
                         const QRec64 q = rec[qs];
@@ -783,32 +784,36 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
     // ones run nearly alone; each wave therefore lowers its priority by one
     // step per quarter of its share done, keeping the waves of a SIMD at
     // similar progress so they finish together.
-    const long long w =
-        (long long)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long u0 = (w * total) / nwaves, u1 = ((w + 1) * total) / nwaves;
     pr_step = (int)max(1LL, min((u1 - u0) / 4, (long long)INT_MAX));
     pr_next = pr_step;
     set_prio(3);
     if (u0 < u1) run_range(u0, u1);
-    if (COUNT_OVL && lane == 0 && ovl_acc) atomicAdd(&ctr->overlap, ovl_acc);
+    if (lane == 0 && w < sl.nwaves) {
+        sl.slab_n[w] = n_own;
+        if (COUNT_OVL) sl.wave_ovl[w] = ovl_acc;
+    }
 }
 
 // Selected pairs -> hits: the pinned binary64 decision again (a selected
 // pair of the binary32 filter may be a miss) and, for hits, the interval.
-// One thread per selected pair, grid-stride over the list.
-__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
-                                                const Cand *__restrict__ cand,
-                                                unsigned long long cand_cap, DevIndex ix,
-                                                Hit24 *__restrict__ out, unsigned long long cap,
-                                                Counters *__restrict__ ctr) {
-    const unsigned long long n = min((unsigned long long)ctr->cand, cand_cap);
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    for (unsigned long long k0 = (unsigned long long)blockIdx.x * blockDim.x; k0 < n; k0 += stride) {
-        const unsigned long long k = k0 + threadIdx.x;
+// One wave per slab (grid-stride); the hits of slab s are compacted to the
+// front of hit slab s with a ballot, so no atomics are needed.
+__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec, Slabs sl,
+                                                DevIndex ix, const Counters *__restrict__ ctr) {
+    const int lane = threadIdx.x & 63;
+    const long long spill_cap = (sl.nslabs - sl.nwaves) * kSlab;
+    const long long stored = min((long long)ctr->spill, spill_cap);
+    const long long nsl = sl.nwaves + (stored + kSlab - 1) / kSlab;
+    const long long nw = (long long)gridDim.x * 4;
+    for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
+        const int cnt = s < sl.nwaves
+                            ? sl.slab_n[s]
+                            : (int)min((long long)kSlab, stored - (s - sl.nwaves) * kSlab);
         bool hit = false;
         Hit24 h;
-        if (k < n) {
-            const Cand c = cand[k];
+        if (lane < cnt) {
+            const Cand c = sl.cand[s * kSlab + lane];
             const QRec64 q = rec[c.q];
             const int e = (int)c.e;
             const Pair64 p = decide64(q, ix.t0[e], ix.t1[e], ix.x0[e], ix.y0[e], ix.z0[e], ix.vx[e],
@@ -819,7 +824,48 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
             h.ta = h.tb = 0.0;
             if (hit) interval64(p, &h.ta, &h.tb);
         }
-        append(hit, h, out, cap, &ctr->hits);
+        const unsigned long long m = __ballot(hit);
+        if (hit) {
+            const unsigned rank = __builtin_amdgcn_mbcnt_hi(
+                (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            sl.hits[s * kSlab + rank] = h;
+        }
+        if (lane == 0) sl.slab_h[s] = __popcll(m);
+    }
+}
+
+// One block: offsets of the hit slabs, the hit and selection totals, and
+// (when the pair kernel counted them) the overlapping pairs.
+__global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
+                                                         int count_ovl) {
+    const long long spill_cap = (sl.nslabs - sl.nwaves) * kSlab;
+    const long long stored = min((long long)ctr->spill, spill_cap);
+    const long long nsl = sl.nwaves + (stored + kSlab - 1) / kSlab;
+    const long long per = (nsl + kScanBlock - 1) / kScanBlock;
+    const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
+    long long sum = 0;
+    for (long long k = lo; k < hi; ++k) sum += sl.slab_h[k];
+    long long tot;
+    long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
+    for (long long k = lo; k < hi; ++k) {
+        sl.hit_off[k] = run;
+        run += sl.slab_h[k];
+    }
+    long long sel = 0;
+    long long ovl = 0;
+    for (int k = threadIdx.x; k < sl.nwaves; k += kScanBlock) {
+        sel += sl.slab_n[k];
+        if (count_ovl) ovl += (long long)sl.wave_ovl[k];
+    }
+    long long sel_tot, ovl_tot;
+    (void)block_exclusive_scan<kScanBlock>(sel, &sel_tot);
+    (void)block_exclusive_scan<kScanBlock>(ovl, &ovl_tot);
+    if (threadIdx.x == 0) {
+        sl.hit_off[nsl] = tot;
+        ctr->hits = (unsigned long long)tot;
+        ctr->cand = (unsigned long long)sel_tot + ctr->spill;
+        ctr->n_slabs = (unsigned long long)nsl;
+        if (count_ovl) ctr->overlap = (unsigned long long)ovl_tot;
     }
 }
 
@@ -843,31 +889,62 @@ static int resident_blocks(K kernel, int block) {
 }
 
 template <int MODE, int BLOCK>
-static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int kernel_overlap, Cand *cand,
-                                unsigned long long cap, hipStream_t st, int *grid_used) {
+static int pair_grid_b(int grid, int kernel_overlap) {
     constexpr int EPT = ept_for_mode(MODE);
+    if (grid > 0) return grid;
     if (kernel_overlap) {
-        auto k = k_pair<MODE, BLOCK, EPT, true>;
-        static const int resident = resident_blocks(k, BLOCK);
-        *grid_used = grid > 0 ? grid : resident;
-        hipLaunchKernelGGL(k, dim3(*grid_used), dim3(BLOCK), 0, st, b.rec_s, b.box_s, b.tiles,
-                           b.unit_off, ix, cand, cap, b.ctr);
-    } else {
-        auto k = k_pair<MODE, BLOCK, EPT, false>;
-        static const int resident = resident_blocks(k, BLOCK);
-        *grid_used = grid > 0 ? grid : resident;
-        hipLaunchKernelGGL(k, dim3(*grid_used), dim3(BLOCK), 0, st, b.rec_s, b.box_s, b.tiles,
-                           b.unit_off, ix, cand, cap, b.ctr);
+        static const int resident = resident_blocks(k_pair<MODE, BLOCK, EPT, true>, BLOCK);
+        return resident;
     }
+    static const int resident = resident_blocks(k_pair<MODE, BLOCK, EPT, false>, BLOCK);
+    return resident;
+}
+
+int pair_grid(int mode, int block, int grid, int kernel_overlap) {
+#define TDS_GRID_CASE(M, BS) \
+    case BS: return pair_grid_b<M, BS>(grid, kernel_overlap);
+    if (mode == kModeFP64) {
+        switch (block) {
+            TDS_GRID_CASE(kModeFP64, 64)
+            TDS_GRID_CASE(kModeFP64, 128)
+            TDS_GRID_CASE(kModeFP64, 256)
+            TDS_GRID_CASE(kModeFP64, 512)
+            TDS_GRID_CASE(kModeFP64, 1024)
+        }
+    } else {
+        switch (block) {
+            TDS_GRID_CASE(kModeFP32Refine, 64)
+            TDS_GRID_CASE(kModeFP32Refine, 128)
+            TDS_GRID_CASE(kModeFP32Refine, 256)
+            TDS_GRID_CASE(kModeFP32Refine, 512)
+            TDS_GRID_CASE(kModeFP32Refine, 1024)
+        }
+    }
+#undef TDS_GRID_CASE
+    return 0;
+}
+
+template <int MODE, int BLOCK>
+static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int kernel_overlap, Slabs sl,
+                                hipStream_t st) {
+    constexpr int EPT = ept_for_mode(MODE);
+    const int g = pair_grid_b<MODE, BLOCK>(grid, kernel_overlap);
+    if ((long long)g * (BLOCK / 64) != sl.nwaves || sl.nslabs <= sl.nwaves)
+        return hipErrorInvalidValue;  // slabs sized for another launch
+    if (kernel_overlap)
+        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, true>), dim3(g), dim3(BLOCK), 0, st, b.rec_s,
+                           b.box_s, b.tiles, b.unit_off, ix, sl, b.ctr);
+    else
+        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, false>), dim3(g), dim3(BLOCK), 0, st, b.rec_s,
+                           b.box_s, b.tiles, b.unit_off, ix, sl, b.ctr);
     TDS_LAUNCH_CHECK();
 }
 
 hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int kernel_overlap,
-                       Cand *cand, unsigned long long cap, hipStream_t st, int *grid_used) {
-    *grid_used = 0;
+                       Slabs sl, hipStream_t st) {
     if (b.nq == 0) return hipSuccess;
 #define TDS_PAIR_CASE(M, BS) \
-    case BS: return launch_pair_b<M, BS>(b, ix, grid, kernel_overlap, cand, cap, st, grid_used);
+    case BS: return launch_pair_b<M, BS>(b, ix, grid, kernel_overlap, sl, st);
     if (mode == kModeFP64) {
         switch (block) {
             TDS_PAIR_CASE(kModeFP64, 64)
@@ -889,12 +966,11 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_refine(DevBatch b, DevIndex ix, const Cand *cand, unsigned long long cand_cap,
-                         Hit24 *out, unsigned long long cap, hipStream_t st) {
+hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st) {
     if (b.nq == 0) return hipSuccess;
     static const int grid = resident_blocks(k_refine, 256);
-    hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec_s, cand, cand_cap, ix, out,
-                       cap, b.ctr);
+    hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec_s, sl, ix, b.ctr);
+    hipLaunchKernelGGL(k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr, count_ovl);
     TDS_LAUNCH_CHECK();
 }
 
@@ -905,6 +981,8 @@ __global__ void k_reset_counters(Counters *c, int all) {
     if (all) {
         c->cand = 0;
         c->overlap = 0;
+        c->spill = 0;
+        c->n_slabs = 0;
     }
 }
 
@@ -914,25 +992,33 @@ hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st) {
 }
 
 // --------------------------------------------------------------- translate
-__global__ void k_translate(const Hit24 *__restrict__ in, int64_t n, const int32_t *__restrict__ perm,
-                            DevIndex ix, int64_t *out) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    Hit24 h = in[k];
-    int64_t *o = out + 5 * k;
-    o[0] = perm[h.q];
-    o[1] = ix.orig[h.e];
-    o[2] = ix.traj[h.e];
-    o[3] = __double_as_longlong(h.ta);
-    o[4] = __double_as_longlong(h.tb);
+// One wave per hit slab: its hits go to their dense positions (the slab's
+// offset plus rank), the first n of them as caller-index records.
+__global__ __launch_bounds__(256) void k_translate(Slabs sl, const Counters *__restrict__ ctr,
+                                                   int64_t n, const int32_t *__restrict__ perm,
+                                                   DevIndex ix, int64_t *out) {
+    const int lane = threadIdx.x & 63;
+    const long long nsl = (long long)ctr->n_slabs;
+    const long long nw = (long long)gridDim.x * 4;
+    for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
+        const long long k = sl.hit_off[s] + lane;
+        if (lane < sl.slab_h[s] && k < n) {
+            const Hit24 h = sl.hits[s * kSlab + lane];
+            int64_t *o = out + 5 * k;
+            o[0] = perm[h.q];
+            o[1] = ix.orig[h.e];
+            o[2] = ix.traj[h.e];
+            o[3] = __double_as_longlong(h.ta);
+            o[4] = __double_as_longlong(h.tb);
+        }
+    }
 }
 
-hipError_t launch_translate(const Hit24 *in, int64_t n, const int32_t *perm, DevIndex ix,
-                            void *out_hits, hipStream_t st) {
+hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
+                            DevIndex ix, void *out_hits, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    int blk = 256;
-    int64_t grid = (n + blk - 1) / blk;
-    hipLaunchKernelGGL(k_translate, dim3((unsigned)grid), dim3(blk), 0, st, in, n, perm, ix,
+    static const int grid = resident_blocks(k_translate, 256);
+    hipLaunchKernelGGL(k_translate, dim3(grid), dim3(256), 0, st, sl, ctr, n, perm, ix,
                        (int64_t *)out_hits);
     TDS_LAUNCH_CHECK();
 }

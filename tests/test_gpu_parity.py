@@ -150,16 +150,27 @@ def test_c5_requests_reduced():
 
 
 def test_overflow_retry():
+    # Every temporally overlapping pair hits, so one work unit selects up to
+    # 256 pairs: more than a wave's slab of 64, the rest spills, and with room
+    # for one spilled selection the search must grow and run again.
+    db, q = fx.all_hit(n_e=4096, n_q=16)
+    want = oracle.search(db, q)
+    assert len(want) > 5000
+    for mode in MODES:
+        got, st, _ = run(db, q, 8, mode=mode, capacity=1, max_retries=2)
+        compare(got, want, db, f"retry {mode}")
+        assert st["retries"] == 1
+        assert st["n_refine"] >= len(want)
+    with pytest.raises(tds.TdsError) as e:
+        run(db, q, 8, capacity=1, max_retries=0)
+    assert e.value.code == L.TDS_EOVERFLOW
+    # a dense box under the same small capacity
     db, q = fx.dense_box(ntraj=200, L=30, box=4.0, nq=20, seed=41, d=1.5)
     want = oracle.search(db, q)
     assert len(want) > 1000
     for mode in MODES:
-        got, st, _ = run(db, q, 30, mode=mode, capacity=1, max_retries=2)
-        compare(got, want, db, f"retry {mode}")
-        assert st["retries"] == 1
-    with pytest.raises(tds.TdsError) as e:
-        run(db, q, 30, capacity=1, max_retries=0)
-    assert e.value.code == L.TDS_EOVERFLOW
+        got, st, _ = run(db, q, 30, mode=mode, capacity=1, max_retries=4)
+        compare(got, want, db, f"dense box {mode}")
 
 
 def test_empty_inputs():
