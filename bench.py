@@ -34,11 +34,12 @@ METRIC = "segment-pair tests/s + p99 query latency; FP32+FP64-refine vs FP64, ex
 D_VALUES = (1.0, 5.0, 25.0)
 NUM_BINS = 1000
 
-# MI355X figures used for the roofline (published / derived from unit counts):
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s for
-# single (non-packed, non-fused) binary32 or binary64 operations; binary64 FMA
-# counts 2 flops -> 78.6 TFLOP/s (the published FP64 vector peak).
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X peaks (published figures, and the unit counts behind them): binary32
+# vector 157.3 TFLOP/s counts an FMA as 2, i.e. 78.6e12 single binary32
+# operations/s (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz; a dependent-free loop
+# of the filter's own instruction mix measured 2.2 cycles per wave64 binary32
+# instruction per SIMD); binary64 vector 78.6 TFLOP/s (FMA = 2).
+FP32_OPS_PEAK = 256 * 4 * 32 * 2.4e9
 FP64_PEAK = 78.6e12
 # Algorithmic work per temporally overlapping pair:
 FP64_FLOPS_PER_PAIR = 49          # binary64 decision, FMA = 2
@@ -298,21 +299,23 @@ def main():
 
     for name, r in results.items():  # each form against its own peak
         if name == "fp32_refine":
-            r["roofline_frac"] = FILTER_OPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3) / VALU_LANE_OPS
+            r["roofline_frac"] = FILTER_OPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3) / FP32_OPS_PEAK
         else:
             r["roofline_frac"] = FP64_FLOPS_PER_PAIR * n_ovl / (r["pair_ms"] / 1e3) / FP64_PEAK
     head_name = "fp32_refine" if "fp32_refine" in results else list(results)[0]
     head = results[head_name]
     if head_name == "fp32_refine":
         ach = FILTER_OPS_PER_PAIR * head["n_eval"] / (head["pair_ms"] / 1e3)
-        roof = dict(bound="alu", achieved=ach / 1e12, peak=VALU_LANE_OPS / 1e12, unit="TFLOP/s",
-                    frac=ach / VALU_LANE_OPS, traffic=measured_traffic("k_pair_fp32_c2_hbm.txt"),
+        roof = dict(bound="alu", achieved=ach / 1e12, peak=FP32_OPS_PEAK / 1e12, unit="TFLOP/s",
+                    frac=ach / FP32_OPS_PEAK, traffic=measured_traffic("k_pair_fp32_c2_hbm.txt"),
+                    traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                     kernel="k_pair<fp32_refine>", per_unit=f"{FILTER_OPS_PER_PAIR} binary32 ops per candidate pair",
                     units_per_launch=head["n_eval"], launch_ms=head["pair_ms"])
     else:
         ach = FP64_FLOPS_PER_PAIR * n_ovl / (head["pair_ms"] / 1e3)
         roof = dict(bound="alu", achieved=ach / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
                     frac=ach / FP64_PEAK, traffic=measured_traffic("k_pair_fp64_c2_hbm.txt"),
+                    traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                     kernel="k_pair<fp64>",
                     per_unit=f"{FP64_FLOPS_PER_PAIR} binary64 flops per overlapping pair",
                     units_per_launch=n_ovl, launch_ms=head["pair_ms"])

@@ -130,7 +130,7 @@ struct tds_query {
     int32_t cap_q = 0;        // query slots allocated
     int32_t cap_buckets = 0;  // bucket slots allocated
     DBuf rec, box, rec_s, box_s, first, last, first_s, last_s, key, perm;
-    DBuf bcount, bj2, bcursor, bq_off, tiles, units, unit_off, ctr;
+    DBuf qrank, bcount, bj2, bq_off, tiles, units, unit_off, ctr;
     DBuf qstage, cand, hits, slab_n, slab_h, hit_off, wave_ovl, out_stage;
     Slabs sl{};                    // slab view of the buffers above
     long long nslabs_alloc = 0;    // slabs the cand / hits buffers hold
@@ -419,7 +419,7 @@ void tds_query_destroy(tds_query *q) {
     if (!q) return;
     if (q->pending) (void)hipStreamSynchronize(q->stream);
     for (DBuf *b : {&q->rec, &q->box, &q->rec_s, &q->box_s, &q->first, &q->last, &q->first_s,
-                    &q->last_s, &q->key, &q->perm, &q->bcount, &q->bj2, &q->bcursor, &q->bq_off,
+                    &q->last_s, &q->key, &q->perm, &q->qrank, &q->bcount, &q->bj2, &q->bq_off,
                     &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
                     &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage})
         b->release();
@@ -439,7 +439,7 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
         HIP_TRY(q->rec_s.ensure(n1 * sizeof(QRec64)));
         HIP_TRY(q->box.ensure(n * sizeof(QCube32)));
         HIP_TRY(q->box_s.ensure(n1 * sizeof(QCube32)));
-        for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->key, &q->perm})
+        for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->key, &q->perm, &q->qrank})
             HIP_TRY(b->ensure(n * 4));
         HIP_TRY(q->tiles.ensure(n1 * sizeof(Tile)));
         HIP_TRY(q->units.ensure(n1 * 8));
@@ -449,7 +449,7 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
     }
     if (nbuckets > q->cap_buckets) {
         size_t n = (size_t)nbuckets;
-        for (DBuf *b : {&q->bcount, &q->bj2, &q->bcursor, &q->bq_off}) HIP_TRY(b->ensure(n * 4));
+        for (DBuf *b : {&q->bcount, &q->bj2, &q->bq_off}) HIP_TRY(b->ensure(n * 4));
         q->cap_buckets = nbuckets;
     }
     return TDS_OK;
@@ -594,7 +594,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.perm = q->perm.as<int32_t>();
     b.bcount = q->bcount.as<int32_t>();
     b.bj2 = q->bj2.as<int32_t>();
-    b.bcursor = q->bcursor.as<int32_t>();
+    b.qrank = q->qrank.as<int32_t>();
     b.bq_off = q->bq_off.as<int32_t>();
     b.tiles = q->tiles.as<Tile>();
     b.units = q->units.as<long long>();

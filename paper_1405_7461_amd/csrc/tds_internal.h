@@ -127,7 +127,8 @@ struct DevBatch {
     int32_t *first_s, *last_s;  // sorted order
     int32_t *key;               // caller order bucket (-1: no candidates)
     int32_t *perm;              // perm[sorted position] = caller index
-    int32_t *bcount, *bj2, *bcursor, *bq_off;  // per bucket
+    int32_t *qrank;             // caller order rank within its bucket
+    int32_t *bcount, *bj2, *bq_off;  // per bucket
     Tile *tiles;
     long long *units;           // per tile (periodic)
     long long *unit_off;        // exclusive scan of units per tile (+ total)

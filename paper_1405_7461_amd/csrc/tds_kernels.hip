@@ -127,7 +127,6 @@ __global__ void k_zero_batch(DevBatch b) {
     for (int k = i; k < b.nbuckets; k += gridDim.x * blockDim.x) {
         b.bcount[k] = 0;
         b.bj2[k] = -1;
-        b.bcursor[k] = 0;
     }
     if (i == 0) {
         Counters z = {};
@@ -271,7 +270,7 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
             double u = floor((s0 - ix.t_first) / ix.width);
             key = u <= 0.0 ? 0 : (u >= (double)(b.nbuckets - 1) ? b.nbuckets - 1 : (int)u);
         }
-        if (key >= 0) atomicAdd(&b.bcount[key], 1);
+        b.qrank[i] = key >= 0 ? atomicAdd(&b.bcount[key], 1) : 0;
         b.key[i] = key;
     }
     novl = wave_sum_u64(novl);
@@ -375,13 +374,14 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
 }
 
 // One thread per query segment with candidates: place it at its bucket's
-// next free position and move its record, box and range there.
+// offset plus the rank the histogram gave it, and move its record, box and
+// range there.
 __global__ void k_scatter(DevBatch b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.nq) return;
     int k = b.key[i];
     if (k < 0) return;
-    int pos = b.bq_off[k] + atomicAdd(&b.bcursor[k], 1);
+    int pos = b.bq_off[k] + b.qrank[i];
     b.perm[pos] = i;
     b.rec_s[pos] = b.rec[i];
     b.box_s[pos] = b.box[i];
@@ -608,8 +608,14 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                                                 Slabs sl, Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
     const long long nwaves = (long long)gridDim.x * (BLOCK / 64);
+    // Workgroups are dealt to the 8 XCDs in turn (block b on XCD b % 8), each
+    // XCD with its own L2. Numbering the waves XCD by XCD gives every XCD one
+    // contiguous eighth of the work units, so the tiles' query records and
+    // entry chunks are fetched into one L2 rather than into all eight.
+    const int g_all = (int)gridDim.x, g_x = (int)blockIdx.x % 8;
+    const int lblock = g_x * (g_all / 8) + min(g_x, g_all % 8) + (int)blockIdx.x / 8;
     const long long w =
-        (long long)blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        (long long)lblock * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long total = rfl64((long long)ctr->n_units);
     const int ntiles = __builtin_amdgcn_readfirstlane((int)ctr->n_tiles);
     unsigned long long ovl_acc = 0;
