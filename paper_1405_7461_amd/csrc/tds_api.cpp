@@ -129,7 +129,7 @@ struct tds_query {
     tds_index *ix = nullptr;
     int32_t cap_q = 0;        // query slots allocated
     int32_t cap_buckets = 0;  // bucket slots allocated
-    DBuf rec, box, rec_s, box_s, first, last, first_s, last_s, key, perm;
+    DBuf rec, box, first, last, first_s, last_s, key, perm;
     DBuf qrank, bcount, bj2, bq_off, tiles, units, unit_off, ctr;
     DBuf qstage, cand, hits, slab_n, slab_h, hit_off, wave_ovl, out_stage;
     Slabs sl{};                    // slab view of the buffers above
@@ -418,7 +418,7 @@ int tds_query_create(tds_index *ix, tds_query **out) {
 void tds_query_destroy(tds_query *q) {
     if (!q) return;
     if (q->pending) (void)hipStreamSynchronize(q->stream);
-    for (DBuf *b : {&q->rec, &q->box, &q->rec_s, &q->box_s, &q->first, &q->last, &q->first_s,
+    for (DBuf *b : {&q->rec, &q->box, &q->first, &q->last, &q->first_s,
                     &q->last_s, &q->key, &q->perm, &q->qrank, &q->bcount, &q->bj2, &q->bq_off,
                     &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
                     &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage})
@@ -436,11 +436,10 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
         int32_t c = std::max<int32_t>(nq, std::max<int32_t>(1024, q->cap_q + q->cap_q / 2));
         size_t n = (size_t)c, n1 = n + 1;
         HIP_TRY(q->rec.ensure(n * sizeof(QRec64)));
-        HIP_TRY(q->rec_s.ensure(n1 * sizeof(QRec64)));
         HIP_TRY(q->box.ensure(n * sizeof(QCube32)));
-        HIP_TRY(q->box_s.ensure(n1 * sizeof(QCube32)));
-        for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->key, &q->perm, &q->qrank})
+        for (DBuf *b : {&q->first, &q->last, &q->first_s, &q->last_s, &q->key, &q->qrank})
             HIP_TRY(b->ensure(n * 4));
+        HIP_TRY(q->perm.ensure((n + 2) * 4));  // read-ahead slots
         HIP_TRY(q->tiles.ensure(n1 * sizeof(Tile)));
         HIP_TRY(q->units.ensure(n1 * 8));
         HIP_TRY(q->unit_off.ensure(n1 * 8));
@@ -583,9 +582,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.ntiles_cap = o.tiling == TDS_TILE_PERIODIC ? (nq + o.batch_size - 1) / o.batch_size : nq;
     b.count_overlap = (o.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0;
     b.rec = q->rec.as<QRec64>();
-    b.rec_s = q->rec_s.as<QRec64>();
     b.box = q->box.as<QCube32>();
-    b.box_s = q->box_s.as<QCube32>();
     b.first = q->first.as<int32_t>();
     b.last = q->last.as<int32_t>();
     b.first_s = q->first_s.as<int32_t>();

@@ -121,12 +121,12 @@ struct DevBatch {
     int32_t ntiles_cap;
     int32_t count_overlap;      // exact overlap count in the query preparation
     int32_t pad;
-    QRec64 *rec, *rec_s;  // caller order, sorted order (+1 padding slot)
-    QCube32 *box, *box_s;
+    QRec64 *rec;          // caller order
+    QCube32 *box;         // caller order
     int32_t *first, *last;      // caller order candidate range (last < first: empty)
     int32_t *first_s, *last_s;  // sorted order
     int32_t *key;               // caller order bucket (-1: no candidates)
-    int32_t *perm;              // perm[sorted position] = caller index
+    int32_t *perm;              // perm[sorted position] = caller index (+2 spare slots)
     int32_t *qrank;             // caller order rank within its bucket
     int32_t *bcount, *bj2, *bq_off;  // per bucket
     Tile *tiles;

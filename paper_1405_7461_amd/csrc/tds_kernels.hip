@@ -184,8 +184,6 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         }
         __syncthreads();
     }
-    const double *bpend = in_lds ? s_bins : ix.bpend;
-    const double *bstart = in_lds ? s_bins + ix.nb : ix.bstart;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long novl = 0;
     if (i < b.nq) {
@@ -245,13 +243,14 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         // Candidate bins: j1 = first bin whose running maximum end exceeds
         // t0, j2 = last bin whose start is below t1 (spans must overlap with
         // positive length).
-        int j1 = first_greater(bpend, ix.nb, s0);
-        int lo = 0, hi = ix.nb;  // number of bins with start < t1
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (bstart[mid] < s1) lo = mid + 1; else hi = mid;
+        int j1, j2;
+        if (in_lds) {
+            j1 = first_greater(s_bins, ix.nb, s0);
+            j2 = (int)count_less(s_bins + ix.nb, ix.nb, s1) - 1;
+        } else {
+            j1 = first_greater(ix.bpend, ix.nb, s0);
+            j2 = (int)count_less(ix.bstart, ix.nb, s1) - 1;
         }
-        int j2 = lo - 1;
         bool any = ok && j1 <= j2;
         b.first[i] = any ? ix.bfirst[j1] : 0;
         b.last[i] = any ? ix.blast[j2] : -1;
@@ -374,8 +373,8 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
 }
 
 // One thread per query segment with candidates: place it at its bucket's
-// offset plus the rank the histogram gave it, and move its record, box and
-// range there.
+// offset plus the rank the histogram gave it (the kernels after this read
+// its record and cube through perm).
 __global__ void k_scatter(DevBatch b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.nq) return;
@@ -383,8 +382,6 @@ __global__ void k_scatter(DevBatch b) {
     if (k < 0) return;
     int pos = b.bq_off[k] + b.qrank[i];
     b.perm[pos] = i;
-    b.rec_s[pos] = b.rec[i];
-    b.box_s[pos] = b.box[i];
     b.first_s[pos] = b.first[i];
     b.last_s[pos] = b.last[i];
 }
@@ -603,6 +600,7 @@ __device__ __forceinline__ long long rfl64(long long v) {
 template <int MODE, int BLOCK, int EPT, bool COUNT_OVL>
 __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                                                 const QCube32 *__restrict__ box,
+                                                const int32_t *__restrict__ perm, int nq,
                                                 const Tile *__restrict__ tiles,
                                                 const long long *__restrict__ unit_off, DevIndex ix,
                                                 Slabs sl, Counters *__restrict__ ctr) {
@@ -691,10 +689,18 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 }
                 auto walk = [&](auto full) {
                     constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
-                    QRec64 qn = rec[qb];
+                    // Records in caller order through perm, read one query
+                    // ahead (and perm two ahead). perm carries two spare slots;
+                    // positions past the placed segments hold no index, so
+                    // the read-ahead clamps it.
+                    auto clampq = [&](int i) { return min(max(i, 0), nq - 1); };
+                    QRec64 qn = rec[clampq(perm[qb])];
+                    int pnext = perm[qb + 1];
                     for (int qs = qb; qs < qe; ++qs) {
                         const QRec64 q = qn;
-                        qn = rec[qs + 1];  // prefetch (the sorted arrays carry one spare slot)
+                        const int pn = pnext;
+                        pnext = perm[qs + 2];
+                        qn = rec[clampq(pn)];
                         progress();
 #pragma unroll
                         for (int j = 0; j < EPT; ++j) {
@@ -745,7 +751,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             select(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
                     }
                     if (COUNT_OVL) {
-                        const QRec64 q = rec[qs];
+                        const QRec64 q = rec[perm[qs]];
 #pragma unroll
                         for (int j = 0; j < EPT; ++j) {
                             const int e = wb + j * 64 + lane;
@@ -765,7 +771,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     for (int s0 = qb; s0 < qe; s0 += kStage) {
                         const int ns = __builtin_amdgcn_readfirstlane(min(kStage, qe - s0));
                         if (lane < ns) {
-                            const QCube32 c = box[s0 + lane];
+                            const QCube32 c = box[perm[s0 + lane]];
                             s_q[wv][lane] = make_float4(c.cx, c.cy, c.cz, c.r);
                         }
 #pragma unroll 2
@@ -805,7 +811,8 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
 // pair of the binary32 filter may be a miss) and, for hits, the interval.
 // One wave per slab (grid-stride); the hits of slab s are compacted to the
 // front of hit slab s with a ballot, so no atomics are needed.
-__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec, Slabs sl,
+__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
+                                                const int32_t *__restrict__ perm, Slabs sl,
                                                 DevIndex ix, const Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
     const long long spill_cap = (sl.nslabs - sl.nwaves) * kSlab;
@@ -820,7 +827,7 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec, 
         Hit24 h;
         if (lane < cnt) {
             const Cand c = sl.cand[s * kSlab + lane];
-            const QRec64 q = rec[c.q];
+            const QRec64 q = rec[perm[c.q]];
             const int e = (int)c.e;
             const Pair64 p = decide64(q, ix.t0[e], ix.t1[e], ix.x0[e], ix.y0[e], ix.z0[e], ix.vx[e],
                                       ix.vy[e], ix.vz[e]);
@@ -841,7 +848,33 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec, 
 }
 
 // One block: offsets of the hit slabs, the hit and selection totals, and
-// (when the pair kernel counted them) the overlapping pairs.
+// (when the pair kernel counted them) the overlapping pairs. Each thread
+// takes a contiguous run of slabs; runs of up to kScanRun are loaded with
+// independent reads (one memory latency), longer ones in a loop.
+constexpr int kScanRun = 8;
+
+template <class T, class F>
+__device__ __forceinline__ long long run_sum(const T *a, long long lo, long long hi, F &&each) {
+    long long sum = 0;
+    if (hi - lo <= kScanRun) {
+        T v[kScanRun];
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j) v[j] = lo + j < hi ? a[lo + j] : T(0);
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j)
+            if (lo + j < hi) {
+                each(lo + j, sum);
+                sum += (long long)v[j];
+            }
+    } else {
+        for (long long k = lo; k < hi; ++k) {
+            each(k, sum);
+            sum += (long long)a[k];
+        }
+    }
+    return sum;
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
                                                          int count_ovl) {
     const long long spill_cap = (sl.nslabs - sl.nwaves) * kSlab;
@@ -849,20 +882,16 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
     const long long nsl = sl.nwaves + (stored + kSlab - 1) / kSlab;
     const long long per = (nsl + kScanBlock - 1) / kScanBlock;
     const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
-    long long sum = 0;
-    for (long long k = lo; k < hi; ++k) sum += sl.slab_h[k];
+    auto none = [](long long, long long) {};
+    const long long sum = run_sum(sl.slab_h, lo, hi, none);
     long long tot;
-    long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
-    for (long long k = lo; k < hi; ++k) {
-        sl.hit_off[k] = run;
-        run += sl.slab_h[k];
-    }
-    long long sel = 0;
-    long long ovl = 0;
-    for (int k = threadIdx.x; k < sl.nwaves; k += kScanBlock) {
-        sel += sl.slab_n[k];
-        if (count_ovl) ovl += (long long)sl.wave_ovl[k];
-    }
+    const long long base = block_exclusive_scan<kScanBlock>(sum, &tot);
+    (void)run_sum(sl.slab_h, lo, hi, [&](long long k, long long pre) { sl.hit_off[k] = base + pre; });
+    const long long per_w = (sl.nwaves + kScanBlock - 1) / kScanBlock;
+    const long long wlo = min((long long)sl.nwaves, (long long)threadIdx.x * per_w);
+    const long long whi = min((long long)sl.nwaves, wlo + per_w);
+    const long long sel = run_sum(sl.slab_n, wlo, whi, none);
+    const long long ovl = count_ovl ? run_sum(sl.wave_ovl, wlo, whi, none) : 0;
     long long sel_tot, ovl_tot;
     (void)block_exclusive_scan<kScanBlock>(sel, &sel_tot);
     (void)block_exclusive_scan<kScanBlock>(ovl, &ovl_tot);
@@ -938,11 +967,11 @@ static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int kernel_ov
     if ((long long)g * (BLOCK / 64) != sl.nwaves || sl.nslabs <= sl.nwaves)
         return hipErrorInvalidValue;  // slabs sized for another launch
     if (kernel_overlap)
-        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, true>), dim3(g), dim3(BLOCK), 0, st, b.rec_s,
-                           b.box_s, b.tiles, b.unit_off, ix, sl, b.ctr);
+        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, true>), dim3(g), dim3(BLOCK), 0, st, b.rec,
+                           b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
     else
-        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, false>), dim3(g), dim3(BLOCK), 0, st, b.rec_s,
-                           b.box_s, b.tiles, b.unit_off, ix, sl, b.ctr);
+        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, false>), dim3(g), dim3(BLOCK), 0, st, b.rec,
+                           b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
     TDS_LAUNCH_CHECK();
 }
 
@@ -975,7 +1004,7 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
 hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st) {
     if (b.nq == 0) return hipSuccess;
     static const int grid = resident_blocks(k_refine, 256);
-    hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec_s, sl, ix, b.ctr);
+    hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix, b.ctr);
     hipLaunchKernelGGL(k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr, count_ovl);
     TDS_LAUNCH_CHECK();
 }
