@@ -6,11 +6,13 @@ package is its Python binding. See include/tds.h for the C ABI.
 from .api import (  # noqa: F401
     Hits,
     Index,
+    Prepared,
     Query,
     build_index,
     fetch_results,
     plan_bins,
     plan_ranges,
+    prepare,
     query_batch,
     search,
 )

@@ -142,6 +142,37 @@ def _bins_array(cbins, n) -> np.ndarray:
     return np.frombuffer(bytes(cbins)[: n * BIN_DTYPE.itemsize], dtype=BIN_DTYPE).copy()
 
 
+class Prepared:
+    """Query segments and thresholds marshalled once for repeated batches.
+
+    Holds the tds_segments struct, the threshold pointer and references that
+    keep the arrays alive; passing it to Query.batch skips the per-call
+    conversion (the library reads the same memory again, so arrays changed in
+    place are seen by the next batch).
+    """
+
+    def __init__(self, q, d):
+        s, keep, mem = _segments(q, with_traj=False)
+        if mem == L.TDS_MEM_DEVICE:
+            import torch
+            dd = d if _is_torch(d) else torch.as_tensor(np.broadcast_to(d, (s.n,)), dtype=torch.float64,
+                                                        device=q.x0.device)
+            dd = dd.to(torch.float64).contiguous()
+            if dd.numel() != s.n:
+                dd = dd.expand(s.n).contiguous()
+            dptr = dd.data_ptr()
+        else:
+            dd = np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.float64), (s.n,)))
+            dptr = dd.ctypes.data
+        keep.append(dd)
+        self.segments, self.dptr, self.keep, self.mem = s, dptr, keep, mem
+        self.n = int(s.n)
+
+
+def prepare(q, d) -> Prepared:
+    return Prepared(q, d)
+
+
 class Query:
     """One query handle (tds_query_create): buffers reused across batches."""
 
@@ -157,19 +188,8 @@ class Query:
     def batch(self, q, d, mode="fp64", tiling="periodic", batch_size=0, block_size=0,
               capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False,
               kernel_overlap=False, stream=None):
-        s, keep, mem = _segments(q, with_traj=False)
-        if mem == L.TDS_MEM_DEVICE:
-            import torch
-            dd = d if _is_torch(d) else torch.as_tensor(np.broadcast_to(d, (s.n,)), dtype=torch.float64,
-                                                        device=q.x0.device)
-            dd = dd.to(torch.float64).contiguous()
-            if dd.numel() != s.n:
-                dd = dd.expand(s.n).contiguous()
-            dptr = dd.data_ptr()
-        else:
-            dd = np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.float64), (s.n,)))
-            dptr = dd.ctypes.data
-        keep.append(dd)
+        p = q if isinstance(q, Prepared) else Prepared(q, d)
+        s, dptr, keep = p.segments, p.dptr, p.keep
         flags = ((L.TDS_QF_TIMING if timing else 0) | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
                  | (L.TDS_QF_KERNEL_OVERLAP if kernel_overlap else 0))
         o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,

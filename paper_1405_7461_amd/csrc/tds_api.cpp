@@ -448,7 +448,8 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
     }
     if (nbuckets > q->cap_buckets) {
         size_t n = (size_t)nbuckets;
-        for (DBuf *b : {&q->bcount, &q->bj2, &q->bq_off}) HIP_TRY(b->ensure(n * 4));
+        for (DBuf *b : {&q->bcount, &q->bq_off}) HIP_TRY(b->ensure(n * kBucketSub * 4));
+        HIP_TRY(q->bj2.ensure(n * 4));
         q->cap_buckets = nbuckets;
     }
     return TDS_OK;

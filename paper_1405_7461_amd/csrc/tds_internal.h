@@ -110,6 +110,11 @@ struct DevIndex {
 
 // Range buckets per first candidate bin: spans of 0, 1, 2 and >= 3 bins.
 constexpr int kSpanClasses = 4;
+// Each bucket may count its query segments on kBucketSub counters (segment i
+// on counter i % kBucketSub) to spread atomics on one bucket over several
+// addresses; the bucket's segments stay contiguous in the sorted order. One
+// counter measured fastest on MI355X (the histogram is not bound by them).
+constexpr int kBucketSub = 1;
 
 // Query-side buffers of one batch (device).
 struct DevBatch {
@@ -128,7 +133,8 @@ struct DevBatch {
     int32_t *key;               // caller order bucket (-1: no candidates)
     int32_t *perm;              // perm[sorted position] = caller index (+2 spare slots)
     int32_t *qrank;             // caller order rank within its bucket
-    int32_t *bcount, *bj2, *bq_off;  // per bucket
+    int32_t *bcount, *bq_off;   // per bucket and sub-counter (kBucketSub each)
+    int32_t *bj2;               // per bucket
     Tile *tiles;
     long long *units;           // per tile (periodic)
     long long *unit_off;        // exclusive scan of units per tile (+ total)

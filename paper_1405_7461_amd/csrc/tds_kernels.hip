@@ -125,7 +125,8 @@ int nbuckets_for(int tiling, int nb, int m) {
 __global__ void k_zero_batch(DevBatch b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     for (int k = i; k < b.nbuckets; k += gridDim.x * blockDim.x) {
-        b.bcount[k] = 0;
+#pragma unroll
+        for (int c = 0; c < kBucketSub; ++c) b.bcount[k * kBucketSub + c] = 0;
         b.bj2[k] = -1;
     }
     if (i == 0) {
@@ -174,6 +175,15 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
                         const double *__restrict__ qx1, const double *__restrict__ qy1,
                         const double *__restrict__ qz1, const double *__restrict__ qt1,
                         const double *__restrict__ qd, DevBatch b, DevIndex ix) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // the segment's inputs are requested before the block waits for the bins
+    double a0 = 0.0, b0 = 0.0, c0 = 0.0, s0 = 0.0, a1 = 0.0, b1 = 0.0, c1 = 0.0, s1 = 1.0;
+    double d = 0.0;
+    if (i < b.nq) {
+        a0 = qx0[i], b0 = qy0[i], c0 = qz0[i], s0 = qt0[i];
+        a1 = qx1[i], b1 = qy1[i], c1 = qz1[i], s1 = qt1[i];
+        d = qd[i];
+    }
     // Small bin tables are searched in LDS (one coalesced copy per block).
     extern __shared__ double s_bins[];  // running maximum ends, then starts
     const bool in_lds = ix.nb <= kQprepLdsBins;
@@ -184,12 +194,8 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         }
         __syncthreads();
     }
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long novl = 0;
     if (i < b.nq) {
-        double a0 = qx0[i], b0 = qy0[i], c0 = qz0[i], s0 = qt0[i];
-        double a1 = qx1[i], b1 = qy1[i], c1 = qz1[i], s1 = qt1[i];
-        double d = qd[i];
         bool ok = isfinite(a0) && isfinite(b0) && isfinite(c0) && isfinite(s0) && isfinite(a1) &&
                   isfinite(b1) && isfinite(c1) && isfinite(s1) && isfinite(d) && d >= 0.0 &&
                   s1 > s0;
@@ -269,7 +275,7 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
             double u = floor((s0 - ix.t_first) / ix.width);
             key = u <= 0.0 ? 0 : (u >= (double)(b.nbuckets - 1) ? b.nbuckets - 1 : (int)u);
         }
-        b.qrank[i] = key >= 0 ? atomicAdd(&b.bcount[key], 1) : 0;
+        b.qrank[i] = key >= 0 ? atomicAdd(&b.bcount[key * kBucketSub + (i % kBucketSub)], 1) : 0;
         b.key[i] = key;
     }
     novl = wave_sum_u64(novl);
@@ -317,34 +323,87 @@ __device__ __forceinline__ void bucket_range(const DevBatch &b, const DevIndex &
 // tiling each non-empty bucket is a tile of nchunk * nq work units, and the
 // tiles' unit offsets are scanned here as well.
 constexpr int kScanBlock = 1024;
+// Each thread takes a contiguous run of buckets; runs of up to kBucketRun
+// have their counts and ranges read with loads issued together and kept in
+// registers for both passes (longer runs read them again).
+constexpr int kBucketRun = 4;
+
 __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex ix) {
     const int n = b.nbuckets;
     const int per = (n + kScanBlock - 1) / kScanBlock;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
     const bool range = b.tiling == kTileRange;
+    const bool held = per <= kBucketRun;
+    int hc[kBucketRun], he0[kBucketRun], hne[kBucketRun];
+    auto count_of = [&](int k) {
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < kBucketSub; ++j) c += b.bcount[k * kBucketSub + j];
+        return c;
+    };
+    if (held) {
+        int j2r[kBucketRun];
+#pragma unroll
+        for (int r = 0; r < kBucketRun; ++r) {
+            const int k = lo + r;
+            hc[r] = k < hi ? count_of(k) : 0;
+            he0[r] = hne[r] = 0;
+            j2r[r] = -1;
+            if (range && k < hi) {
+                const int j1 = k / kSpanClasses, cls = k - j1 * kSpanClasses;
+                j2r[r] = cls < kSpanClasses - 1 ? j1 + cls : b.bj2[k];
+                he0[r] = ix.bfirst[j1];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kBucketRun; ++r)
+            if (range && lo + r < hi && hc[r] > 0) hne[r] = ix.blast[j2r[r]] - he0[r] + 1;
+    }
+    auto get = [&](int r, int *c, int *e0, int *ne) {  // bucket lo + r
+        if (held) {
+            *c = hc[r];
+            *e0 = he0[r];
+            *ne = hne[r];
+        } else {
+            *c = count_of(lo + r);
+            *e0 = *ne = 0;
+            if (range && *c > 0) bucket_range(b, ix, lo + r, e0, ne);
+        }
+    };
     long long c_sum = 0, t_sum = 0, u_sum = 0;
     unsigned long long ev = 0;
-    for (int k = lo; k < hi; ++k) {
-        int c = b.bcount[k];
+    auto tally = [&](int r) {
+        int c, e0, ne;
+        get(r, &c, &e0, &ne);
         c_sum += c;
         if (range && c > 0) {
-            int e0, ne;
-            bucket_range(b, ix, k, &e0, &ne);
             t_sum += 1;
             u_sum += (long long)((ne + b.chunk - 1) / b.chunk) * c;
             ev += (unsigned long long)c * (unsigned long long)ne;
         }
+    };
+    if (held) {  // unrolled, so the held values stay in registers
+#pragma unroll
+        for (int r = 0; r < kBucketRun; ++r)
+            if (lo + r < hi) tally(r);
+    } else {
+        for (int r = 0; r < hi - lo; ++r) tally(r);
     }
     long long c_tot, t_tot, u_tot;
     long long c_run = block_exclusive_scan<kScanBlock>(c_sum, &c_tot);
     long long t_run = block_exclusive_scan<kScanBlock>(t_sum, &t_tot);
     long long u_run = block_exclusive_scan<kScanBlock>(u_sum, &u_tot);
-    for (int k = lo; k < hi; ++k) {
-        int c = b.bcount[k];
-        b.bq_off[k] = (int)c_run;
+    auto place = [&](int r) {
+        const int k = lo + r;
+        int c, e0, ne;
+        get(r, &c, &e0, &ne);
+        int part = 0;
+#pragma unroll
+        for (int j = 0; j < kBucketSub; ++j) {
+            b.bq_off[k * kBucketSub + j] = (int)c_run + part;
+            if (kBucketSub > 1) part += b.bcount[k * kBucketSub + j];
+        }
         if (range && c > 0) {
-            int e0, ne;
-            bucket_range(b, ix, k, &e0, &ne);
             Tile tl;
             tl.q0 = (int)c_run;
             tl.nq = c;
@@ -359,6 +418,13 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
             u_run += (long long)tl.nchunk * c;
         }
         c_run += c;
+    };
+    if (held) {
+#pragma unroll
+        for (int r = 0; r < kBucketRun; ++r)
+            if (lo + r < hi) place(r);
+    } else {
+        for (int r = 0; r < hi - lo; ++r) place(r);
     }
     ev = wave_sum_u64(ev);
     if (lane_id() == 0 && ev) atomicAdd(&b.ctr->n_eval, ev);
@@ -380,7 +446,7 @@ __global__ void k_scatter(DevBatch b) {
     if (i >= b.nq) return;
     int k = b.key[i];
     if (k < 0) return;
-    int pos = b.bq_off[k] + b.qrank[i];
+    int pos = b.bq_off[k * kBucketSub + (i % kBucketSub)] + b.qrank[i];
     b.perm[pos] = i;
     b.first_s[pos] = b.first[i];
     b.last_s[pos] = b.last[i];
@@ -849,31 +915,10 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
 
 // One block: offsets of the hit slabs, the hit and selection totals, and
 // (when the pair kernel counted them) the overlapping pairs. Each thread
-// takes a contiguous run of slabs; runs of up to kScanRun are loaded with
-// independent reads (one memory latency), longer ones in a loop.
+// takes a contiguous run of slabs and of wave slabs; runs of up to kScanRun
+// are read with independent loads issued together (one memory latency for
+// the whole kernel), longer ones in a loop.
 constexpr int kScanRun = 8;
-
-template <class T, class F>
-__device__ __forceinline__ long long run_sum(const T *a, long long lo, long long hi, F &&each) {
-    long long sum = 0;
-    if (hi - lo <= kScanRun) {
-        T v[kScanRun];
-#pragma unroll
-        for (int j = 0; j < kScanRun; ++j) v[j] = lo + j < hi ? a[lo + j] : T(0);
-#pragma unroll
-        for (int j = 0; j < kScanRun; ++j)
-            if (lo + j < hi) {
-                each(lo + j, sum);
-                sum += (long long)v[j];
-            }
-    } else {
-        for (long long k = lo; k < hi; ++k) {
-            each(k, sum);
-            sum += (long long)a[k];
-        }
-    }
-    return sum;
-}
 
 __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
                                                          int count_ovl) {
@@ -882,16 +927,44 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
     const long long nsl = sl.nwaves + (stored + kSlab - 1) / kSlab;
     const long long per = (nsl + kScanBlock - 1) / kScanBlock;
     const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
-    auto none = [](long long, long long) {};
-    const long long sum = run_sum(sl.slab_h, lo, hi, none);
-    long long tot;
-    const long long base = block_exclusive_scan<kScanBlock>(sum, &tot);
-    (void)run_sum(sl.slab_h, lo, hi, [&](long long k, long long pre) { sl.hit_off[k] = base + pre; });
     const long long per_w = (sl.nwaves + kScanBlock - 1) / kScanBlock;
     const long long wlo = min((long long)sl.nwaves, (long long)threadIdx.x * per_w);
     const long long whi = min((long long)sl.nwaves, wlo + per_w);
-    const long long sel = run_sum(sl.slab_n, wlo, whi, none);
-    const long long ovl = count_ovl ? run_sum(sl.wave_ovl, wlo, whi, none) : 0;
+    long long sum = 0, sel = 0, ovl = 0, tot;
+    if (per <= kScanRun && per_w <= kScanRun) {
+        int h[kScanRun], c[kScanRun];
+        unsigned long long o[kScanRun];
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j) {
+            h[j] = lo + j < hi ? sl.slab_h[lo + j] : 0;
+            c[j] = wlo + j < whi ? sl.slab_n[wlo + j] : 0;
+            o[j] = count_ovl && wlo + j < whi ? sl.wave_ovl[wlo + j] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j) {
+            sum += h[j];
+            sel += c[j];
+            ovl += (long long)o[j];
+        }
+        long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j)
+            if (lo + j < hi) {
+                sl.hit_off[lo + j] = run;
+                run += h[j];
+            }
+    } else {
+        for (long long k = lo; k < hi; ++k) sum += sl.slab_h[k];
+        for (long long k = wlo; k < whi; ++k) {
+            sel += sl.slab_n[k];
+            if (count_ovl) ovl += (long long)sl.wave_ovl[k];
+        }
+        long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
+        for (long long k = lo; k < hi; ++k) {
+            sl.hit_off[k] = run;
+            run += sl.slab_h[k];
+        }
+    }
     long long sel_tot, ovl_tot;
     (void)block_exclusive_scan<kScanBlock>(sel, &sel_tot);
     (void)block_exclusive_scan<kScanBlock>(ovl, &ovl_tot);
