@@ -228,6 +228,25 @@ int tds_query_stats(const tds_query *qh, tds_stats *out);
  * query segment of the last batch (caller order, host arrays of n values). */
 int tds_query_ranges(const tds_query *qh, int64_t *first, int64_t *last, int64_t n);
 
+/*
+ * Device memory hook, so that a host framework can serve the library's
+ * device buffers from its own allocator (for example PyTorch's caching
+ * allocator; the paper keeps D resident on the GPU and sizes result memory
+ * ahead of each kernel, Sec. 3 and Sec. 5, which is what these buffers are).
+ * Every device buffer allocated after the call comes from
+ * alloc(bytes, stream, ctx) and goes back through free(ptr, stream, ctx),
+ * where `stream` is the HIP stream of the library call that needed it (the
+ * build or batch stream; NULL for the default stream). A buffer is always
+ * returned to the allocator that made it, so the hook may be changed while
+ * indexes and query handles exist. alloc returning NULL fails the call with
+ * TDS_ENOMEM. Both functions NULL restore hipMalloc / hipFree; exactly one
+ * NULL is TDS_EINVAL. Process-wide; do not call it while another thread is
+ * inside the library. Pinned host memory is not affected.
+ */
+typedef void *(*tds_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*tds_free_fn)(void *ptr, void *stream, void *ctx);
+int tds_set_allocator(tds_alloc_fn alloc, tds_free_fn free_fn, void *ctx);
+
 const char *tds_last_error(void);
 int tds_abi_version(void);
 

@@ -15,5 +15,6 @@ from .api import (  # noqa: F401
     prepare,
     query_batch,
     search,
+    use_torch_allocator,
 )
 from ._lib import TdsError, lib  # noqa: F401

@@ -74,6 +74,10 @@ class tds_bin(C.Structure):
 
 
 # name -> (restype, argtypes); every symbol include/tds.h declares
+# tds_alloc_fn / tds_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 SIGNATURES = {
     "tds_build_index": (C.c_int, [C.POINTER(tds_segments), C.POINTER(tds_index_opts), _P, C.POINTER(_P)]),
     "tds_index_info_get": (C.c_int, [_P, C.POINTER(tds_index_info)]),
@@ -88,6 +92,7 @@ SIGNATURES = {
     "tds_fetch_results": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
     "tds_query_stats": (C.c_int, [_P, C.POINTER(tds_stats)]),
     "tds_query_ranges": (C.c_int, [_P, _P, _P, C.c_int64]),
+    "tds_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "tds_last_error": (C.c_char_p, []),
     "tds_abi_version": (C.c_int, []),
 }

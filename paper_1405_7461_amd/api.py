@@ -298,3 +298,35 @@ def plan_ranges(bins: np.ndarray, t0, t1):
     L.check(L.lib().tds_plan_ranges(b.ctypes.data_as(C.POINTER(L.tds_bin)), b.size, t0.ctypes.data,
                                     t1.ctypes.data, t0.size, first.ctypes.data, last.ctypes.data))
     return first[: t0.size], last[: t0.size]
+
+
+_torch_hooks = None  # the callbacks must outlive their registration
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Serve the library's device buffers from PyTorch's caching allocator.
+
+    Buffers allocated after the call come from torch (and show up in
+    torch.cuda.memory_allocated()); buffers already allocated go back to the
+    allocator that made them. enable=False restores hipMalloc / hipFree.
+    """
+    global _torch_hooks
+    if not enable:
+        L.check(L.lib().tds_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None))
+        return
+    import torch
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      int(stream or 0))
+        except Exception:  # reported to the caller as TDS_ENOMEM
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    hooks = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
+    L.check(L.lib().tds_set_allocator(hooks[0], hooks[1], None))
+    # keep every registered pair: buffers made by an earlier one free through it
+    _torch_hooks = (_torch_hooks or ()) + (hooks,)

@@ -40,27 +40,62 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 // A device allocation that only grows.
+// Device allocator in force (tds_set_allocator); null functions = HIP.
+struct DevAlloc {
+    tds_alloc_fn alloc = nullptr;
+    tds_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+DevAlloc g_alloc;
+// Stream of the library call in progress on this thread (passed to the hook).
+thread_local void *g_call_stream = nullptr;
+
+struct CallStream {  // sets g_call_stream for the duration of a library call
+    void *prev;
+    explicit CallStream(void *s) : prev(g_call_stream) { g_call_stream = s; }
+    ~CallStream() { g_call_stream = prev; }
+};
+
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevAlloc by;          // allocator that made p
+    void *stream = nullptr;
     hipError_t ensure(size_t need) {
         if (need <= bytes && p) return hipSuccess;
         if (p) {
-            hipError_t e = hipFree(p);
+            hipError_t e = free_now();
             if (e != hipSuccess) return e;
-            p = nullptr;
-            bytes = 0;
         }
         size_t nb = std::max<size_t>(need, 256);
-        hipError_t e = hipMalloc(&p, nb);
-        if (e == hipSuccess) bytes = nb;
-        return e;
+        by = g_alloc;
+        stream = g_call_stream;
+        if (by.alloc) {
+            p = by.alloc(nb, stream, by.ctx);
+            if (!p) return hipErrorOutOfMemory;
+        } else {
+            hipError_t e = hipMalloc(&p, nb);
+            if (e != hipSuccess) {
+                p = nullptr;
+                return e;
+            }
+        }
+        bytes = nb;
+        return hipSuccess;
     }
-    void release() {
-        if (p) (void)hipFree(p);
+    hipError_t free_now() {
+        hipError_t e = hipSuccess;
+        if (p) {
+            if (by.free)
+                by.free(p, stream, by.ctx);
+            else
+                e = hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        return e;
     }
+    void release() { (void)free_now(); }
     template <class T>
     T *as() const { return static_cast<T *>(p); }
 };
@@ -148,6 +183,15 @@ struct tds_query {
 extern "C" {
 
 const char *tds_last_error(void) { return g_err.c_str(); }
+
+int tds_set_allocator(tds_alloc_fn alloc, tds_free_fn free_fn, void *ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(TDS_EINVAL, "tds_set_allocator: give both functions or neither");
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return TDS_OK;
+}
 int tds_abi_version(void) { return TDS_ABI_VERSION; }
 
 int tds_plan_bins(const double *t0_sorted, const double *t1_sorted, int64_t n, int32_t num_bins,
@@ -197,6 +241,7 @@ int tds_plan_ranges(const tds_bin *bins, int64_t nb, const double *t0, const dou
 
 int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *stream,
                     tds_index **out) {
+    CallStream call_stream_scope(stream);
     if (!db || !opts || !out) return fail(TDS_EINVAL, "tds_build_index: null argument");
     *out = nullptr;
     if (db->n < 0 || db->n >= (int64_t)INT32_MAX)
@@ -508,6 +553,7 @@ static int launch_search(tds_query *q) {
 
 int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
                     const tds_query_opts *opts, void *stream) {
+    CallStream call_stream_scope(stream);
     if (!q || !qs || !opts || (qs->n > 0 && !d)) return fail(TDS_EINVAL, "tds_query_batch: null argument");
     if (q->pending) return fail(TDS_ESTATE, "tds_query_batch: previous batch not fetched");
     if (qs->n < 0 || qs->n >= (int64_t)INT32_MAX / 2)
@@ -612,6 +658,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
 }
 
 int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total) {
+    CallStream call_stream_scope(q ? (void *)q->stream : nullptr);
     if (!q || !n_total || cap < 0 || (cap > 0 && !out))
         return fail(TDS_EINVAL, "tds_fetch_results: invalid argument");
     if (out_mem != TDS_MEM_HOST && out_mem != TDS_MEM_DEVICE)

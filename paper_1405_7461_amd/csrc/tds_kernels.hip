@@ -798,9 +798,8 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         eh[j] = make_float2(NAN, NAN);
                     }
                 }
-                auto test_query = [&](const float4 &qc, const int qs, auto full) {
+                auto gaps_of = [&](const float4 &qc, float (&gap)[EPT], auto full) {
                     constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
-                    float gap[EPT];
                     gap[0] = cube_gap(ec[0], eh[0], qc);  // slot 0 always holds entries
                     float gmin = gap[0];
 #pragma unroll
@@ -811,11 +810,14 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             gmin = fminf(gmin, gap[j]);
                         }
                     }
-                    if (__builtin_expect(__ballot(gmin <= qc.w) != 0ull, 0)) {  // rare
+                    return gmin;
+                };
+                auto emit = [&](const float4 &qc, const int qs, const float (&gap)[EPT]) {
 #pragma unroll
-                        for (int j = 0; j < EPT; ++j)
-                            select(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
-                    }
+                    for (int j = 0; j < EPT; ++j)
+                        select(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                };
+                auto count_ovl = [&](const int qs) {
                     if (COUNT_OVL) {
                         const QRec64 q = rec[perm[qs]];
 #pragma unroll
@@ -827,10 +829,12 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     }
                 };
                 // The wave stages up to 64 query cubes in its LDS slice (one
-                // coalesced load, lane i takes cube s0 + i), then walks them with
-                // broadcast LDS reads; the other waves of the SIMD cover their
-                // latency. LDS requests of one wave complete in order, so the
-                // slice is rewritten only after the previous walk has read it.
+                // coalesced load, lane i takes cube s0 + i), then walks them two
+                // at a time with broadcast LDS reads: the gaps of both are
+                // computed before the one (rarely taken) branch, which gives the
+                // scheduler two independent chains. LDS requests of one wave
+                // complete in order, so the slice is rewritten only after the
+                // previous walk has read it.
                 __shared__ float4 s_q[BLOCK / 64][kStage];
                 const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
                 auto walk = [&](auto full) {
@@ -840,9 +844,26 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             const QCube32 c = box[perm[s0 + lane]];
                             s_q[wv][lane] = make_float4(c.cx, c.cy, c.cz, c.r);
                         }
-#pragma unroll 2
-                        for (int j = 0; j < ns; ++j) {
-                            test_query(s_q[wv][j], s0 + j, full);
+                        int j = 0;
+                        for (; j + 1 < ns; j += 2) {
+                            const float4 qa = s_q[wv][j], qz = s_q[wv][j + 1];
+                            float ga[EPT], gz[EPT];
+                            const float ma = gaps_of(qa, ga, full), mz = gaps_of(qz, gz, full);
+                            if (__builtin_expect(__ballot(ma <= qa.w || mz <= qz.w) != 0ull, 0)) {
+                                emit(qa, s0 + j, ga);
+                                emit(qz, s0 + j + 1, gz);
+                            }
+                            count_ovl(s0 + j);
+                            count_ovl(s0 + j + 1);
+                            progress();
+                            progress();
+                        }
+                        if (j < ns) {
+                            const float4 qa = s_q[wv][j];
+                            float ga[EPT];
+                            const float ma = gaps_of(qa, ga, full);
+                            if (__builtin_expect(__ballot(ma <= qa.w) != 0ull, 0)) emit(qa, s0 + j, ga);
+                            count_ovl(s0 + j);
                             progress();
                         }
                     }

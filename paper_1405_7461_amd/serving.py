@@ -145,6 +145,20 @@ class Server:
         r.est_bytes = HIT_BYTES * self.k_safety * max(1.0, self.alpha.expected_hits(r.seg.t0, r._n_eval_seg))
 
     # -------------------------------------------------------------- running
+    def warmup(self, requests: Sequence[Request]) -> None:
+        """Run the requests once on every executor, untimed and unrecorded.
+
+        Grows each query handle's device buffers to the sizes these requests
+        need, so that a measured run does not pay first-use allocations.
+        The hit-rate estimates learnt here are kept; the batch log is not.
+        """
+        for ex in self.executors:
+            for r in requests:
+                self.plan(r)
+                cap = int(r.est_bytes / HIT_BYTES) + 1024
+                ex(r.seg, np.broadcast_to(r.d, (r.n,)).astype(np.float64), cap)
+        self.batches.clear()
+
     def run(self, requests: Sequence[Request], time_scale: float = 1.0) -> Dict:
         """Serve requests at their arrival times (seconds x time_scale)."""
         reqs = sorted(requests, key=lambda r: r.arrival)

@@ -128,3 +128,13 @@ def test_build_index_validates_before_the_device():
     with pytest.raises(tds.TdsError) as e:
         tds.build_index(bad2, 10)
     assert e.value.code == L.TDS_EINVAL
+
+
+def test_set_allocator_arguments():
+    lib = L.lib()
+    assert lib.tds_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None) == L.TDS_OK
+    rc = lib.tds_set_allocator(L.ALLOC_FN(lambda n, s, c: None), L.FREE_FN(), None)
+    assert rc == L.TDS_EINVAL and b"both" in lib.tds_last_error()
+    rc = lib.tds_set_allocator(L.ALLOC_FN(), L.FREE_FN(lambda p, s, c: None), None)
+    assert rc == L.TDS_EINVAL
+    assert lib.tds_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None) == L.TDS_OK

@@ -252,3 +252,28 @@ def test_host_query_validation():
         run(db, q.with_d(-1.0), 4, index=ix)
     with pytest.raises(tds.TdsError):
         run(db, q, 4, index=ix, block_size=96)
+
+
+def test_torch_allocator_hook():
+    """Device buffers served by torch's caching allocator give the same hits."""
+    import torch
+    db, q, m = gen.make_config("C1")
+    want = oracle.search(db, q)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    tds.use_torch_allocator()
+    try:
+        ix = tds.build_index(db, m)
+        during_index = torch.cuda.memory_allocated()
+        assert during_index - before >= len(db) * 64  # the binary64 entry arrays at least
+        for mode in MODES:
+            got, st, _ = run(db, q, m, index=ix, mode=mode)
+            compare(got, want, db, f"torch allocator {mode}")
+        ix.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() <= before + (1 << 20)
+    finally:
+        tds.use_torch_allocator(False)
+    # buffers made afterwards come from HIP again
+    got, st, _ = run(db, q, m)
+    compare(got, want, db, "hip allocator again")
