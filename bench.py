@@ -163,6 +163,67 @@ def cpu_baseline(db, q, n_ovl_total, target_s=10.0):
                 seconds=dt)
 
 
+def trajectory_form(ix, db, dq, q, opts, log_fn=log, steps=10, warmup=2):
+    """Trajectory-level answers: the segment hits of a batch merged per
+    (query trajectory, entry trajectory) into maximal intervals, on the
+    headline batch and on a hit-dense batch (every database trajectory
+    shifted by 0.5 along x, d = 5: about one million segment hits)."""
+    import torch
+    import paper_1405_7461_amd as tds
+    stream = torch.cuda.current_stream()
+    per_d = len(q) // len(D_VALUES)
+    # each (query trajectory, d) is one query: the copy index goes into the high bits
+    head_ids = q.traj + (np.repeat(np.arange(len(D_VALUES), dtype=np.int64), per_d) << 32)
+    shifted = db.subset(np.arange(len(db))).with_d(5.0)
+    shifted.x0 = shifted.x0 + 0.5
+    shifted.x1 = shifted.x1 + 0.5
+    cases = [("C2 headline batch (120,000 query segments, ids per trajectory and d)", dq, head_ids),
+             ("hit-dense: the 2,500 database trajectories shifted by 0.5 in x, d = 5 "
+              "(1,000,000 query segments)", to_device(shifted), shifted.traj)]
+    out = []
+    for label, qdev, ids in cases:
+        qh = tds.Query(ix)
+        prep = tds.prepare(qdev, qdev.d)
+        ids_dev = torch.as_tensor(ids, device="cuda")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        wall, gpu, seg_ms = [], [], []
+        for i in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qh.batch(prep, None, stream=stream, **opts)
+            h = qh.fetch(out="device")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ev0.record(stream)
+            u = qh.fetch_trajectories(ids_dev, out="device")
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if i >= warmup:
+                seg_ms.append((t1 - t0) * 1e3)
+                wall.append((t2 - t1) * 1e3)
+                gpu.append(ev0.elapsed_time(ev1))
+        n_hit, n_out = len(h), len(u)
+        st = qh.stats()
+        qh.close()
+        merge_ms = float(np.mean(gpu))
+        # algorithmic bytes: per segment hit its 24-B record, two 8-B trajectory
+        # ids and the 4-B query permutation; per merged interval a 32-B record
+        alg = 44 * n_hit + 32 * n_out
+        r = dict(workload=label, n_segment_hits=n_hit, n_intervals=n_out,
+                 step_ms_segments=float(np.mean(seg_ms)), merge_ms_gpu=merge_ms,
+                 merge_ms_wall=float(np.mean(wall)), retries=int(st["retries"]),
+                 segment_hits_per_s=n_hit / (merge_ms / 1e3),
+                 roofline=dict(bound="hbm", achieved=alg / (merge_ms / 1e3) / 1e9, peak=8000.0,
+                               unit="GB/s", frac=alg / (merge_ms / 1e3) / 8e12,
+                               per_unit="44 B per segment hit + 32 B per merged interval"))
+        log_fn(f"trajectories [{label[:24]}]: {n_hit} segment hits -> {n_out} intervals, merge "
+               f"{merge_ms:.3f} ms GPU / {r['merge_ms_wall']:.3f} ms wall, segment step "
+               f"{r['step_ms_segments']:.3f} ms, retries {r['retries']}")
+        out.append(r)
+    return out
+
+
 def batching_form(log_fn=log, reps=10):
     """C4: uneven query set, per-query d, one persistent launch, autotuned."""
     import torch
@@ -231,6 +292,8 @@ def serving_form(log_fn=log, n_requests=400, rates=(0.5, 0.8, 0.95)):
         st = srv.run(reqs)
         srv.close()
         runs.append(dict(rate_frac=f, rate_req_s=f * sat_rate, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                         p99_wait_ms=st["p99_wait_ms"], p99_service_ms=st["p99_service_ms"],
+                         retries=st["retries"],
                          pair_tests_s=sum(r.n_overlap for r in reqs) / st["wall_s"],
                          mean_batch_requests=st["mean_batch_requests"], batches=st["n_batches"]))
         log_fn(f"serving at {f:.2f} x saturation ({f * sat_rate:.0f} req/s): p50 {st['p50_ms']:.3f} ms, "
@@ -264,6 +327,7 @@ def main():
     ap.add_argument("--forms", default="fp32_refine,fp64")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-trajectories", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the forms, run a plain device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters)")
@@ -347,6 +411,8 @@ def main():
         "roofline": roof,
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "opts"} for k, v in results.items()},
     }
+    if not args.no_trajectories:
+        line["trajectories"] = trajectory_form(ix, db, dq, q, forms["fp32_refine"])
     if not args.no_batching:
         line["batching"] = batching_form()
     if not args.no_serving:

@@ -229,6 +229,36 @@ int tds_query_stats(const tds_query *qh, tds_stats *out);
 int tds_query_ranges(const tds_query *qh, int64_t *first, int64_t *last, int64_t n);
 
 /*
+ * Trajectory-level answer of the last batch (Sec. 3: per query trajectory,
+ * the entry trajectories within d and the times when). For each pair
+ * (query trajectory, entry trajectory) the segment-pair intervals are merged
+ * into maximal closed intervals (intervals that overlap or touch merge).
+ */
+typedef struct {
+    int64_t query_traj; /* the query segments' trajectory id, as given */
+    int64_t entry_traj; /* the entry segments' trajectory id (tds_segments.traj_id) */
+    double t_a, t_b;    /* one maximal interval */
+} tds_traj_hit;         /* 32 bytes */
+
+/*
+ * Complete the last batch like tds_fetch_results (waiting, and re-running on
+ * overflow), then merge its hits per trajectory pair on the device.
+ * query_traj: the trajectory id of each query segment of the batch (n values,
+ * caller order) in memory space traj_mem. Writes min(cap, n) records, sorted
+ * by (query_traj, entry_traj, t_a), to `out` in memory space out_mem;
+ * *n_total receives the number of merged intervals (cap = 0 sizes). Usable
+ * before or after tds_fetch_results for the same batch. A call with ids
+ * merges; a call with query_traj == NULL copies the records the last merge
+ * of this batch left in the handle (TDS_ESTATE if there is none), so
+ * sizing and copying cost one merge. Device output is written on the
+ * batch's stream; host output is complete on return. Errors: TDS_EINVAL
+ * for a null n_total, cap < 0, cap > 0 with a null out, a bad memory space;
+ * TDS_ESTATE without a batch; TDS_EDEVICE for a failed device call.
+ */
+int tds_fetch_trajectories(tds_query *qh, const int64_t *query_traj, int32_t traj_mem,
+                           tds_traj_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total);
+
+/*
  * Device memory hook, so that a host framework can serve the library's
  * device buffers from its own allocator (for example PyTorch's caching
  * allocator; the paper keeps D resident on the GPU and sizes result memory

@@ -8,10 +8,12 @@ from .api import (  # noqa: F401
     Index,
     Prepared,
     Query,
+    TrajHits,
     build_index,
     fetch_results,
     plan_bins,
     plan_ranges,
+    point_segments,
     prepare,
     query_batch,
     search,

@@ -54,6 +54,11 @@ class tds_hit(C.Structure):
                 ("t_a", C.c_double), ("t_b", C.c_double)]
 
 
+class tds_traj_hit(C.Structure):
+    _fields_ = [("query_traj", C.c_int64), ("entry_traj", C.c_int64), ("t_a", C.c_double),
+                ("t_b", C.c_double)]
+
+
 class tds_stats(C.Structure):
     _fields_ = [("n_query", C.c_int64), ("n_eval", C.c_int64), ("n_overlap", C.c_int64),
                 ("n_overlap_k", C.c_int64), ("n_refine", C.c_int64), ("n_hit", C.c_int64),
@@ -91,6 +96,8 @@ SIGNATURES = {
     "tds_query_batch": (C.c_int, [_P, C.POINTER(tds_segments), _P, C.POINTER(tds_query_opts), _P]),
     "tds_fetch_results": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
     "tds_query_stats": (C.c_int, [_P, C.POINTER(tds_stats)]),
+    "tds_fetch_trajectories": (C.c_int, [_P, _P, C.c_int32, _P, C.c_int64, C.c_int32,
+                                         C.POINTER(C.c_int64)]),
     "tds_query_ranges": (C.c_int, [_P, _P, _P, C.c_int64]),
     "tds_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "tds_last_error": (C.c_char_p, []),

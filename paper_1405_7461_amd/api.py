@@ -142,6 +142,36 @@ def _bins_array(cbins, n) -> np.ndarray:
     return np.frombuffer(bytes(cbins)[: n * BIN_DTYPE.itemsize], dtype=BIN_DTYPE).copy()
 
 
+@dataclass
+class TrajHits:
+    """Trajectory-level results: maximal intervals per trajectory pair."""
+    query_traj: object
+    entry_traj: object
+    ta: object
+    tb: object
+
+    def __len__(self):
+        return int(self.query_traj.shape[0])
+
+
+def point_segments(x, y, z, t0, t1):
+    """Stationary query points over [t0, t1] as segments with equal end points.
+
+    A point query is the special case of a query segment whose velocity is
+    zero; the same kernels answer it.
+    """
+    class Seg:
+        pass
+
+    s = Seg()
+    s.x0 = s.x1 = np.ascontiguousarray(x, dtype=np.float64)
+    s.y0 = s.y1 = np.ascontiguousarray(y, dtype=np.float64)
+    s.z0 = s.z1 = np.ascontiguousarray(z, dtype=np.float64)
+    s.t0 = np.ascontiguousarray(t0, dtype=np.float64)
+    s.t1 = np.ascontiguousarray(t1, dtype=np.float64)
+    return s
+
+
 class Prepared:
     """Query segments and thresholds marshalled once for repeated batches.
 
@@ -228,6 +258,46 @@ class Query:
                        arr[:, 3].copy().view(np.float64), arr[:, 4].copy().view(np.float64))
         self._keep = None
         return res
+
+    def fetch_trajectories(self, query_traj, out: str = "host", cap: Optional[int] = None) -> "TrajHits":
+        """Maximal intervals per (query trajectory, entry trajectory) of the batch.
+
+        query_traj: trajectory id of each query segment of the batch (numpy
+        or a CUDA int64 tensor). Sorted by (query_traj, entry_traj, t_a).
+        """
+        if _is_torch(query_traj):
+            import torch
+            qt = query_traj.to(torch.int64).contiguous()
+            qptr, qmem = qt.data_ptr(), L.TDS_MEM_DEVICE
+        else:
+            qt = np.ascontiguousarray(query_traj, dtype=np.int64)
+            qptr, qmem = qt.ctypes.data, L.TDS_MEM_HOST
+        n = C.c_int64()
+        L.check(L.lib().tds_fetch_trajectories(self._h, C.c_void_p(qptr), qmem, None, 0, L.TDS_MEM_HOST,
+                                               C.byref(n)))
+        total = int(n.value)
+        m = total if cap is None else min(int(cap), total)
+        # the first call merged; a call without ids copies those records
+        if out == "device":
+            import torch
+            buf = torch.empty((max(m, 1), 4), dtype=torch.int64, device="cuda")
+            if m:
+                L.check(L.lib().tds_fetch_trajectories(self._h, None, qmem,
+                                                       C.c_void_p(buf.data_ptr()), m, L.TDS_MEM_DEVICE,
+                                                       C.byref(n)))
+                qs = self._stream
+                if qs is not None and not isinstance(qs, int) and qs != torch.cuda.current_stream():
+                    torch.cuda.current_stream().wait_stream(qs)
+            buf = buf[:m]
+            return TrajHits(buf[:, 0], buf[:, 1], buf[:, 2].view(torch.float64), buf[:, 3].view(torch.float64))
+        arr = np.empty((max(m, 1), 4), dtype=np.int64)
+        if m:
+            L.check(L.lib().tds_fetch_trajectories(self._h, None, qmem,
+                                                   C.c_void_p(arr.ctypes.data), m, L.TDS_MEM_HOST,
+                                                   C.byref(n)))
+        arr = arr[:m]
+        return TrajHits(arr[:, 0].copy(), arr[:, 1].copy(), arr[:, 2].copy().view(np.float64),
+                        arr[:, 3].copy().view(np.float64))
 
     def stats(self) -> dict:
         s = L.tds_stats()

@@ -167,6 +167,7 @@ struct tds_query {
     DBuf rec, box, first, last, first_s, last_s, key, perm;
     DBuf qrank, bcount, bj2, bq_off, tiles, units, unit_off, ctr;
     DBuf qstage, cand, hits, slab_n, slab_h, hit_off, wave_ovl, out_stage;
+    DBuf tr_qtraj, tr_work, tr_temp, tr_out;  // trajectory merge
     Slabs sl{};                    // slab view of the buffers above
     long long nslabs_alloc = 0;    // slabs the cand / hits buffers hold
     int32_t nwaves_alloc = 0;      // wave slabs slab_n / wave_ovl hold
@@ -176,6 +177,8 @@ struct tds_query {
     tds_query_opts opts{};
     int block = 256, grid = 0;
     bool pending = false, fetched = false;
+    bool traj_valid = false;  // tr_out holds the merged records of this batch
+    long long traj_total = 0;
     tds_stats stats{};
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
@@ -466,7 +469,8 @@ void tds_query_destroy(tds_query *q) {
     for (DBuf *b : {&q->rec, &q->box, &q->first, &q->last, &q->first_s,
                     &q->last_s, &q->key, &q->perm, &q->qrank, &q->bcount, &q->bj2, &q->bq_off,
                     &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
-                    &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage})
+                    &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage,
+                    &q->tr_qtraj, &q->tr_work, &q->tr_temp, &q->tr_out})
         b->release();
     if (q->host_ctr) (void)hipHostFree(q->host_ctr);
     for (auto &ev : q->ev)
@@ -500,20 +504,20 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
     return TDS_OK;
 }
 
-// Slab buffers for a pair launch of `nwaves` waves with room for `spill`
-// selections beyond the wave slabs (grown, never shrunk).
+// Slab buffers for a pair launch of `nwaves` waves with `spill` spill slabs
+// after the wave slabs (grown, never shrunk).
 static int ensure_slabs(tds_query *q, int32_t nwaves, unsigned long long spill) {
-    const long long want = (long long)nwaves + 1 + (long long)((spill + kSlab - 1) / kSlab);
+    const long long want = (long long)nwaves + 1 + (long long)spill;
     if (want > q->nslabs_alloc) {
         const long long n = std::max<long long>(want, q->nslabs_alloc + q->nslabs_alloc / 2);
         HIP_TRY(q->cand.ensure((size_t)n * kSlab * sizeof(Cand)));
         HIP_TRY(q->hits.ensure((size_t)n * kSlab * sizeof(Hit24)));
+        HIP_TRY(q->slab_n.ensure((size_t)n * sizeof(int32_t)));
         HIP_TRY(q->slab_h.ensure((size_t)n * sizeof(int32_t)));
         HIP_TRY(q->hit_off.ensure((size_t)(n + 1) * sizeof(long long)));
         q->nslabs_alloc = n;
     }
     if (nwaves > q->nwaves_alloc) {
-        HIP_TRY(q->slab_n.ensure((size_t)nwaves * sizeof(int32_t)));
         HIP_TRY(q->wave_ovl.ensure((size_t)nwaves * sizeof(unsigned long long)));
         q->nwaves_alloc = nwaves;
     }
@@ -530,8 +534,9 @@ static int ensure_slabs(tds_query *q, int32_t nwaves, unsigned long long spill) 
     return TDS_OK;
 }
 
+// Spill slabs available after the wave slabs.
 static unsigned long long spill_capacity(const Slabs &sl) {
-    return (unsigned long long)(sl.nslabs - sl.nwaves) * kSlab;
+    return (unsigned long long)(sl.nslabs - sl.nwaves);
 }
 
 // Pair kernel (selects pairs), then refine (turns them into hits) and the hit
@@ -599,9 +604,10 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     if (grid < 1 || (long long)grid * (o.block_size / 64) > INT32_MAX / kSlab)
         return fail(TDS_EINVAL, "tds_query_batch: grid %d not supported", grid);
     q->grid = grid;
-    // capacity: selections beyond the per-wave slabs to make room for
-    const unsigned long long spill = o.capacity > 0 ? (unsigned long long)o.capacity : (1ull << 20);
-    rc = ensure_slabs(q, grid * (o.block_size / 64), spill);
+    // capacity: selections beyond the per-wave slabs to make room for, in
+    // spill slabs of kSlab
+    const unsigned long long sel = o.capacity > 0 ? (unsigned long long)o.capacity : (1ull << 20);
+    rc = ensure_slabs(q, grid * (o.block_size / 64), (sel + kSlab - 1) / kSlab);
     if (rc) return rc;
 
     const double *qin[8];
@@ -652,26 +658,23 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     if (rc) return rc;
     q->pending = true;
     q->fetched = false;
+    q->traj_valid = false;
     std::memset(&q->stats, 0, sizeof q->stats);
     q->stats.n_query = nq;
     return TDS_OK;
 }
 
-int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total) {
-    CallStream call_stream_scope(q ? (void *)q->stream : nullptr);
-    if (!q || !n_total || cap < 0 || (cap > 0 && !out))
-        return fail(TDS_EINVAL, "tds_fetch_results: invalid argument");
-    if (out_mem != TDS_MEM_HOST && out_mem != TDS_MEM_DEVICE)
-        return fail(TDS_EINVAL, "tds_fetch_results: bad out_mem");
-    if (!q->pending && !q->fetched) return fail(TDS_ESTATE, "tds_fetch_results: no batch");
+// Wait for the pending batch, re-run it on overflow, and fill the stats
+// (shared by the fetch calls). `who` names the caller in error messages.
+static int complete_batch(tds_query *q, const char *who) {
     hipStream_t st = q->stream;
     if (q->pending) {
         HIP_TRY(hipStreamSynchronize(st));
         Counters c = *q->host_ctr;
         if (c.err) {
             q->pending = false;
-            return fail(TDS_EINVAL, "tds_fetch_results: the batch holds an invalid query "
-                                    "segment (non-finite value, t_end <= t_start, or d < 0)");
+            return fail(TDS_EINVAL, "%s: the batch holds an invalid query "
+                                    "segment (non-finite value, t_end <= t_start, or d < 0)", who);
         }
         // Overflow (Sec. 5: re-attempt with more memory): selections beyond
         // the slabs were counted, not stored; grow and run the search again.
@@ -680,12 +683,14 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
             if (retries >= q->opts.max_retries) {
                 q->pending = false;
                 return fail(TDS_EOVERFLOW,
-                            "tds_fetch_results: %llu selections beyond the wave slabs exceed "
-                            "the capacity %llu",
-                            c.spill, spill_capacity(q->sl));
+                            "%s: the selections needed %llu spill slabs of %d records "
+                            "beyond the wave slabs; capacity %llu",
+                            who, c.spill, kSlab, spill_capacity(q->sl));
             }
             ++retries;
-            int rc = ensure_slabs(q, q->sl.nwaves, c.spill + c.spill / 4 + 1024);
+            // the count is exact (a wave's slabs depend only on its own
+            // selections), so this size suffices for the re-run
+            int rc = ensure_slabs(q, q->sl.nwaves, c.spill);
             if (rc) return rc;
             HIP_TRY(launch_reset_counters(q->b.ctr, 1, st));
             rc = launch_search(q);
@@ -711,6 +716,21 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
         q->pending = false;
         q->fetched = true;
     }
+    return TDS_OK;
+}
+
+int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total) {
+    CallStream call_stream_scope(q ? (void *)q->stream : nullptr);
+    if (!q || !n_total || cap < 0 || (cap > 0 && !out))
+        return fail(TDS_EINVAL, "tds_fetch_results: invalid argument");
+    if (out_mem != TDS_MEM_HOST && out_mem != TDS_MEM_DEVICE)
+        return fail(TDS_EINVAL, "tds_fetch_results: bad out_mem");
+    if (!q->pending && !q->fetched) return fail(TDS_ESTATE, "tds_fetch_results: no batch");
+    hipStream_t st = q->stream;
+    if (q->pending) {
+        int rc = complete_batch(q, "tds_fetch_results");
+        if (rc) return rc;
+    }
     int64_t n = q->stats.n_hit;
     *n_total = n;
     int64_t m = std::min<int64_t>(cap, n);
@@ -732,6 +752,85 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
         if (timing) HIP_TRY(hipEventElapsedTime(&q->stats.ms_fetch, q->ev[4], q->ev[5]));
     }
     return TDS_OK;
+}
+
+// min(cap, total) merged records of the batch from the handle to `out`.
+static int copy_traj(tds_query *q, tds_traj_hit *out, int64_t cap, int32_t out_mem,
+                     int64_t *n_total) {
+    *n_total = q->traj_total;
+    const int64_t m = std::min<int64_t>(cap, q->traj_total);
+    if (m > 0) {
+        HIP_TRY(hipMemcpyAsync(out, q->tr_out.p, (size_t)m * sizeof(tds_traj_hit),
+                               out_mem == TDS_MEM_HOST ? hipMemcpyDeviceToHost
+                                                       : hipMemcpyDeviceToDevice,
+                               q->stream));
+        if (out_mem == TDS_MEM_HOST) HIP_TRY(hipStreamSynchronize(q->stream));
+    }
+    return TDS_OK;
+}
+
+int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj_mem,
+                           tds_traj_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total) {
+    CallStream call_stream_scope(q ? (void *)q->stream : nullptr);
+    if (!q || !n_total || cap < 0 || (cap > 0 && !out))
+        return fail(TDS_EINVAL, "tds_fetch_trajectories: invalid argument");
+    if ((traj_mem != TDS_MEM_HOST && traj_mem != TDS_MEM_DEVICE) ||
+        (out_mem != TDS_MEM_HOST && out_mem != TDS_MEM_DEVICE))
+        return fail(TDS_EINVAL, "tds_fetch_trajectories: bad memory space");
+    if (!q->pending && !q->fetched) return fail(TDS_ESTATE, "tds_fetch_trajectories: no batch");
+    if (q->pending) {
+        int rc = complete_batch(q, "tds_fetch_trajectories");
+        if (rc) return rc;
+    }
+    const long long n = q->stats.n_hit;
+    const int32_t nq = q->b.nq;
+    hipStream_t st = q->stream;
+    if (!query_traj) {  // copy the records of the last merge of this batch
+        if (!q->traj_valid)
+            return fail(TDS_ESTATE, "tds_fetch_trajectories: no merge of this batch to copy");
+        return copy_traj(q, out, cap, out_mem, n_total);
+    }
+    *n_total = 0;
+    q->traj_valid = false;
+    if (n == 0) {
+        q->traj_valid = true;
+        q->traj_total = 0;
+        return TDS_OK;
+    }
+    const int64_t *qt = query_traj;
+    if (traj_mem == TDS_MEM_HOST) {
+        HIP_TRY(q->tr_qtraj.ensure((size_t)nq * sizeof(int64_t)));
+        HIP_TRY(hipMemcpyAsync(q->tr_qtraj.p, query_traj, (size_t)nq * sizeof(int64_t),
+                               hipMemcpyHostToDevice, st));
+        qt = q->tr_qtraj.as<int64_t>();
+    }
+    // work arrays, 8-byte ones first: qt, et, ta, tb, key_a, key_b, sta, stb,
+    // runmax (9 x 8 B), then idx_a, idx_b, flag, gid, start, mid (6 x 4 B)
+    const size_t nn = (size_t)n;
+    HIP_TRY(q->tr_work.ensure(nn * (9 * 8 + 6 * 4) + 64));
+    char *w = q->tr_work.as<char>();
+    auto take8 = [&](void *&dst) { dst = w; w += nn * 8; };
+    auto take4 = [&](void *&dst) { dst = w; w += nn * 4; };
+    TrajBufs t{};
+    take8((void *&)t.qt); take8((void *&)t.et); take8((void *&)t.ta); take8((void *&)t.tb);
+    take8((void *&)t.key_a); take8((void *&)t.key_b); take8((void *&)t.sta); take8((void *&)t.stb);
+    take8((void *&)t.runmax);
+    take4((void *&)t.idx_a); take4((void *&)t.idx_b); take4((void *&)t.flag); take4((void *&)t.gid);
+    take4((void *&)t.start); take4((void *&)t.mid);
+    const size_t temp = traj_temp_bytes(n);
+    if (temp == 0) return fail(TDS_EDEVICE, "tds_fetch_trajectories: sort sizing failed");
+    HIP_TRY(q->tr_temp.ensure(temp));
+    HIP_TRY(q->tr_out.ensure(nn * sizeof(tds_traj_hit) + sizeof(long long)));
+    tds_traj_hit *recs = q->tr_out.as<tds_traj_hit>();
+    long long *total_dev = reinterpret_cast<long long *>(recs + nn);
+    HIP_TRY(launch_traj_merge(q->sl, q->b.ctr, n, q->b.perm, qt, q->ix->dev, t, q->tr_temp.p,
+                              q->tr_temp.bytes, recs, total_dev, st));
+    long long total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, total_dev, sizeof total, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    q->traj_total = total;
+    q->traj_valid = true;
+    return copy_traj(q, out, cap, out_mem, n_total);
 }
 
 int tds_query_stats(const tds_query *q, tds_stats *out) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tds.h"
+
 namespace tds {
 
 // Query segment as the binary64 pair test reads it: start point, span,
@@ -55,15 +57,17 @@ struct Hit24 {
 
 // Selected pairs and hits live in slabs of kSlab records. Slab w < nwaves
 // belongs to wave w of the pair launch, which fills it without atomics; a
-// wave whose next selections do not fit its slab appends them to the shared
-// spill slabs after the wave slabs (one atomic per append). Hit slab s holds
-// the hits among selected-pair slab s, and k_hit_scan's offsets give the
-// position of each slab's hits in the dense output.
+// wave whose next selections do not fit its current slab takes a whole new
+// slab from the spill slabs after the wave slabs (one atomic per 64 records
+// at most) and leaves the old one partly filled. Every slab carries its own
+// record count. Hit slab s holds the hits among selected-pair slab s, and
+// k_hit_scan's offsets give the position of each slab's hits in the dense
+// output.
 constexpr int kSlab = 64;
 struct Slabs {
     Cand *cand;                    // nslabs * kSlab
     Hit24 *hits;                   // nslabs * kSlab
-    int32_t *slab_n;               // selected pairs in each wave slab [nwaves]
+    int32_t *slab_n;               // selected pairs in each slab [nslabs]
     int32_t *slab_h;               // hits in each slab [nslabs]
     long long *hit_off;            // exclusive scan of slab_h [nslabs + 1]
     unsigned long long *wave_ovl;  // overlapping pairs counted by each wave [nwaves]
@@ -84,7 +88,7 @@ struct Counters {
     unsigned int n_tiles;
     unsigned int n_sorted;       // query segments placed in tiles
     unsigned int pad;
-    unsigned long long spill;    // selections appended to the spill slabs (may exceed them)
+    unsigned long long spill;    // spill slabs taken by the pair kernel (may exceed nslabs - nwaves)
     unsigned long long n_slabs;  // slabs in use after the refine
 };
 
@@ -141,6 +145,16 @@ struct DevBatch {
     Counters *ctr;
 };
 
+// Work arrays of the trajectory merge (n hits each).
+struct TrajBufs {
+    int64_t *qt, *et;                  // trajectory ids, hit order
+    double *ta, *tb;                   // interval, hit order
+    unsigned long long *key_a, *key_b; // radix-sort keys
+    int32_t *idx_a, *idx_b;            // permutations
+    int32_t *flag, *gid, *start, *mid; // sorted order: pair start, pair id, run start, record no.
+    double *sta, *stb, *runmax;        // sorted order: interval, running maximum of t_b
+};
+
 enum : int { kModeFP64 = 0, kModeFP32Refine = 1 };
 enum : int { kTilePeriodic = 0, kTileRange = 1 };
 
@@ -162,6 +176,13 @@ hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipSt
 hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
                             DevIndex ix, void *out_hits, hipStream_t st);
 hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
+// Trajectory merge (tds_traj.hip): temp bytes for n hits, and the launch
+// (n > 0 hits; writes the merged records to `out` and their number to *total).
+size_t traj_temp_bytes(long long n);
+hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
+                             const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,
+                             size_t temp_bytes, tds_traj_hit *out, long long *total,
+                             hipStream_t st);
 int chunk_for(int mode, int block);
 int nbuckets_for(int tiling, int nb, int m);
 

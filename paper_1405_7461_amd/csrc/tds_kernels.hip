@@ -683,28 +683,31 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
     const long long total = rfl64((long long)ctr->n_units);
     const int ntiles = __builtin_amdgcn_readfirstlane((int)ctr->n_tiles);
     unsigned long long ovl_acc = 0;
-    // Selections go to this wave's slab while they fit, then to the spill
-    // slabs (one atomic per append there).
-    const long long cap = sl.nslabs * kSlab;
-    int n_own = w < sl.nwaves ? 0 : kSlab;  // waves beyond the slabs spill (not launched so)
+    // Selections go to the wave's current slab (its own one first); when a
+    // ballot does not fit, the wave closes that slab with its count and takes
+    // a fresh spill slab with one atomic. A slab number past nslabs is
+    // counted but not stored, so the host can size the re-run exactly: the
+    // number of slabs a wave takes depends only on its own selections.
+    long long cs = w < sl.nwaves ? w : -1;  // waves beyond the slabs (not launched so) spill
+    int cn = w < sl.nwaves ? 0 : kSlab;
     auto select = [&](bool flag, const Cand &rec) {
         const unsigned long long m = __ballot(flag);
         if (m == 0ull) return;
         const int cnt = __popcll(m);
         const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        long long pos;
-        if (n_own + cnt <= kSlab) {
-            pos = w * kSlab + n_own + rank;
-            n_own += cnt;
-        } else {
+        if (cn + cnt > kSlab) {
             const int leader = __ffsll((long long)m) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(&ctr->spill, (unsigned long long)cnt);
-            base = __shfl(base, leader);
-            pos = (long long)sl.nwaves * kSlab + (long long)(base + rank);
+            unsigned long long k = 0;
+            if (lane == leader) {
+                if (cs >= 0 && cs < sl.nslabs) sl.slab_n[cs] = cn;
+                k = atomicAdd(&ctr->spill, 1ull);
+            }
+            cs = (long long)sl.nwaves + (long long)__shfl(k, leader);
+            cn = 0;
         }
-        if (flag && pos < cap) sl.cand[pos] = rec;
+        if (flag && cs < sl.nslabs) sl.cand[cs * kSlab + cn + rank] = rec;
+        cn += cnt;
     };
     // progress-based wave priority (see below): one step down per pr_step units
     int prio = 3, pr_step = 1, pr_next = 1;
@@ -888,10 +891,8 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
     pr_next = pr_step;
     set_prio(3);
     if (u0 < u1) run_range(u0, u1);
-    if (lane == 0 && w < sl.nwaves) {
-        sl.slab_n[w] = n_own;
-        if (COUNT_OVL) sl.wave_ovl[w] = ovl_acc;
-    }
+    if (lane == 0 && cs >= 0 && cs < sl.nslabs) sl.slab_n[cs] = cn;
+    if (COUNT_OVL && lane == 0 && w < sl.nwaves) sl.wave_ovl[w] = ovl_acc;
 }
 
 // Selected pairs -> hits: the pinned binary64 decision again (a selected
@@ -902,14 +903,10 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
                                                 const int32_t *__restrict__ perm, Slabs sl,
                                                 DevIndex ix, const Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
-    const long long spill_cap = (sl.nslabs - sl.nwaves) * kSlab;
-    const long long stored = min((long long)ctr->spill, spill_cap);
-    const long long nsl = sl.nwaves + (stored + kSlab - 1) / kSlab;
+    const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
     const long long nw = (long long)gridDim.x * 4;
     for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
-        const int cnt = s < sl.nwaves
-                            ? sl.slab_n[s]
-                            : (int)min((long long)kSlab, stored - (s - sl.nwaves) * kSlab);
+        const int cnt = sl.slab_n[s];
         bool hit = false;
         Hit24 h;
         if (lane < cnt) {
@@ -943,9 +940,7 @@ constexpr int kScanRun = 8;
 
 __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
                                                          int count_ovl) {
-    const long long spill_cap = (sl.nslabs - sl.nwaves) * kSlab;
-    const long long stored = min((long long)ctr->spill, spill_cap);
-    const long long nsl = sl.nwaves + (stored + kSlab - 1) / kSlab;
+    const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
     const long long per = (nsl + kScanBlock - 1) / kScanBlock;
     const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
     const long long per_w = (sl.nwaves + kScanBlock - 1) / kScanBlock;
@@ -958,7 +953,7 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
 #pragma unroll
         for (int j = 0; j < kScanRun; ++j) {
             h[j] = lo + j < hi ? sl.slab_h[lo + j] : 0;
-            c[j] = wlo + j < whi ? sl.slab_n[wlo + j] : 0;
+            c[j] = lo + j < hi ? sl.slab_n[lo + j] : 0;
             o[j] = count_ovl && wlo + j < whi ? sl.wave_ovl[wlo + j] : 0ull;
         }
 #pragma unroll
@@ -975,11 +970,12 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
                 run += h[j];
             }
     } else {
-        for (long long k = lo; k < hi; ++k) sum += sl.slab_h[k];
-        for (long long k = wlo; k < whi; ++k) {
+        for (long long k = lo; k < hi; ++k) {
+            sum += sl.slab_h[k];
             sel += sl.slab_n[k];
-            if (count_ovl) ovl += (long long)sl.wave_ovl[k];
         }
+        if (count_ovl)
+            for (long long k = wlo; k < whi; ++k) ovl += (long long)sl.wave_ovl[k];
         long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
         for (long long k = lo; k < hi; ++k) {
             sl.hit_off[k] = run;
@@ -992,7 +988,7 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
     if (threadIdx.x == 0) {
         sl.hit_off[nsl] = tot;
         ctr->hits = (unsigned long long)tot;
-        ctr->cand = (unsigned long long)sel_tot + ctr->spill;
+        ctr->cand = (unsigned long long)sel_tot;
         ctr->n_slabs = (unsigned long long)nsl;
         if (count_ovl) ctr->overlap = (unsigned long long)ovl_tot;
     }

@@ -1,0 +1,188 @@
+// Trajectory-level answers on the device: the segment-level hits of a batch
+// merged into maximal intervals per (query trajectory, entry trajectory).
+//
+// The paper's query asks, per query trajectory, for the entry trajectories
+// within d and when (Sec. 3); the segment-pair intervals of one trajectory
+// pair are pieces of that answer, and their union is it. Steps: gather the
+// hits with their two trajectory ids, sort by (query trajectory, entry
+// trajectory, t_a) with three stable radix sorts (least significant key
+// first), then one segmented running maximum of t_b marks where a new
+// maximal interval starts (its t_a lies after every earlier t_b of the pair;
+// closed intervals that touch merge), and a scan of those marks numbers the
+// output records.
+#include <hip/hip_runtime.h>
+
+#include <cstring>  // rocprim's headers use memset
+#include <rocprim/rocprim.hpp>
+
+#include "tds.h"
+#include "tds_internal.h"
+
+namespace tds {
+
+namespace {
+
+__device__ __forceinline__ unsigned long long order_bits(double x) {
+    // ascending unsigned order of binary64 values (no NaN here)
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ unsigned long long order_bits(long long x) {
+    return (unsigned long long)x ^ 0x8000000000000000ull;
+}
+
+// One wave per hit slab: dense hit k gets its trajectories and interval.
+__global__ __launch_bounds__(256) void k_traj_gather(Slabs sl, const Counters *__restrict__ ctr,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int64_t *__restrict__ qtraj_in,
+                                                     DevIndex ix, TrajBufs t) {
+    const int lane = threadIdx.x & 63;
+    const long long nsl = (long long)ctr->n_slabs;
+    const long long nw = (long long)gridDim.x * 4;
+    for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
+        if (lane < sl.slab_h[s]) {
+            const long long k = sl.hit_off[s] + lane;
+            const Hit24 h = sl.hits[s * kSlab + lane];
+            t.qt[k] = qtraj_in[perm[h.q]];
+            t.et[k] = ix.traj[h.e];
+            t.ta[k] = h.ta;
+            t.tb[k] = h.tb;
+            t.key_a[k] = order_bits(h.ta);
+            t.idx_a[k] = (int32_t)k;
+        }
+    }
+}
+
+// key_out[i] = order bits of src[idx[i]] (the next, more significant key).
+__global__ void k_traj_key(const int64_t *__restrict__ src, const int32_t *__restrict__ idx,
+                           unsigned long long *__restrict__ key_out, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key_out[i] = order_bits((long long)src[idx[i]]);
+}
+
+// Sorted order o = idx: pair-start flags and the sorted intervals.
+__global__ void k_traj_flags(TrajBufs t, const int32_t *__restrict__ idx, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t o = idx[i];
+    bool start = i == 0;
+    if (!start) {
+        const int32_t p = idx[i - 1];
+        start = t.qt[o] != t.qt[p] || t.et[o] != t.et[p];
+    }
+    t.flag[i] = start ? 1 : 0;
+    t.sta[i] = t.ta[o];
+    t.stb[i] = t.tb[o];
+}
+
+// A maximal interval starts where the pair starts or t_a exceeds the running
+// maximum of the pair's earlier t_b.
+__global__ void k_traj_starts(TrajBufs t, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool start = t.flag[i] || t.sta[i] > t.runmax[i - 1];
+    t.start[i] = start ? 1 : 0;
+}
+
+// Records: the first member gives the pair and t_a, the last member's
+// running maximum is t_b.
+__global__ void k_traj_emit(TrajBufs t, const int32_t *__restrict__ idx, long long n,
+                            tds_traj_hit *__restrict__ out, long long *__restrict__ total) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long m = (long long)t.mid[i] - 1;
+    if (t.start[i]) {
+        const int32_t o = idx[i];
+        out[m].query_traj = t.qt[o];
+        out[m].entry_traj = t.et[o];
+        out[m].t_a = t.sta[i];
+    }
+    if (i == n - 1 || t.start[i + 1]) out[m].t_b = t.runmax[i];
+    if (i == n - 1) *total = m + 1;
+}
+
+struct MaxOp {
+    __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+};
+struct EqOp {
+    __device__ bool operator()(int32_t a, int32_t b) const { return a == b; }
+};
+
+// All rocprim calls of one merge of n items; temp == nullptr only sizes.
+hipError_t traj_rocprim(TrajBufs t, long long n, void *temp, size_t *temp_bytes, int step,
+                        hipStream_t st) {
+    size_t bytes = *temp_bytes;
+    hipError_t e = hipSuccess;
+    switch (step) {
+    case 0:  // by t_a
+        e = rocprim::radix_sort_pairs(temp, bytes, t.key_a, t.key_b, t.idx_a, t.idx_b, (size_t)n,
+                                      0, 64, st);
+        break;
+    case 1:  // stable by entry trajectory (keys in key_a, values idx_b -> idx_a)
+        e = rocprim::radix_sort_pairs(temp, bytes, t.key_a, t.key_b, t.idx_b, t.idx_a, (size_t)n,
+                                      0, 64, st);
+        break;
+    case 2:  // stable by query trajectory (values idx_a -> idx_b)
+        e = rocprim::radix_sort_pairs(temp, bytes, t.key_a, t.key_b, t.idx_a, t.idx_b, (size_t)n,
+                                      0, 64, st);
+        break;
+    case 3:  // pair ids
+        e = rocprim::inclusive_scan(temp, bytes, t.flag, t.gid, (size_t)n, rocprim::plus<int32_t>(),
+                                    st);
+        break;
+    case 4:  // running maximum of t_b within a pair
+        e = rocprim::inclusive_scan_by_key(temp, bytes, t.gid, t.stb, t.runmax, (size_t)n, MaxOp(),
+                                           EqOp(), st);
+        break;
+    case 5:  // output record numbers
+        e = rocprim::inclusive_scan(temp, bytes, t.start, t.mid, (size_t)n,
+                                    rocprim::plus<int32_t>(), st);
+        break;
+    }
+    *temp_bytes = bytes;
+    return e;
+}
+
+}  // namespace
+
+size_t traj_temp_bytes(long long n) {
+    size_t most = 0;
+    TrajBufs t{};
+    for (int step = 0; step < 6; ++step) {
+        size_t b = 0;
+        if (traj_rocprim(t, n, nullptr, &b, step, 0) != hipSuccess) return 0;
+        most = b > most ? b : most;
+    }
+    return most;
+}
+
+hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
+                             const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,
+                             size_t temp_bytes, tds_traj_hit *out, long long *total,
+                             hipStream_t st) {
+    if (n <= 0) return hipErrorInvalidValue;  // the caller handles a batch without hits
+    const int blk = 256;
+    const unsigned g = (unsigned)((n + blk - 1) / blk);
+    hipLaunchKernelGGL(k_traj_gather, dim3(1024), dim3(256), 0, st, sl, ctr, perm, qtraj, ix, t);
+    hipError_t e;
+    size_t b = temp_bytes;
+    if ((e = traj_rocprim(t, n, temp, &b, 0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_traj_key, dim3(g), dim3(blk), 0, st, t.et, t.idx_b, t.key_a, n);
+    b = temp_bytes;
+    if ((e = traj_rocprim(t, n, temp, &b, 1, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_traj_key, dim3(g), dim3(blk), 0, st, t.qt, t.idx_a, t.key_a, n);
+    b = temp_bytes;
+    if ((e = traj_rocprim(t, n, temp, &b, 2, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_traj_flags, dim3(g), dim3(blk), 0, st, t, t.idx_b, n);
+    b = temp_bytes;
+    if ((e = traj_rocprim(t, n, temp, &b, 3, st)) != hipSuccess) return e;
+    b = temp_bytes;
+    if ((e = traj_rocprim(t, n, temp, &b, 4, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_traj_starts, dim3(g), dim3(blk), 0, st, t, n);
+    b = temp_bytes;
+    if ((e = traj_rocprim(t, n, temp, &b, 5, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_traj_emit, dim3(g), dim3(blk), 0, st, t, t.idx_b, n, out, total);
+    return hipGetLastError();
+}
+
+}  // namespace tds

@@ -256,8 +256,12 @@ class Server:
             raise errors[0]
         wall = now()
         lat = np.array([r.latency for r in reqs])
+        wait = np.array([r.t_admit - r.arrival for r in reqs])
+        service = np.array([r.t_done - r.t_admit for r in reqs])
         return dict(n_requests=len(reqs), wall_s=wall, p50_ms=float(np.percentile(lat, 50) * 1e3),
                     p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                    p99_wait_ms=float(np.percentile(wait, 99) * 1e3),
+                    p99_service_ms=float(np.percentile(service, 99) * 1e3),
                     n_batches=len(self.batches),
                     mean_batch_requests=float(np.mean([b["n_req"] for b in self.batches])),
                     retries=int(sum(b["retries"] for b in self.batches)))

@@ -41,6 +41,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(L.tds_bin) == 40
     assert C.sizeof(L.tds_segments) == 16 + 9 * 8
     assert C.sizeof(L.tds_query_opts) == 6 * 4 + 8 + 2 * 4
+    assert C.sizeof(L.tds_traj_hit) == 32
 
 
 def test_fig1_bin_table():
@@ -138,3 +139,12 @@ def test_set_allocator_arguments():
     rc = lib.tds_set_allocator(L.ALLOC_FN(), L.FREE_FN(lambda p, s, c: None), None)
     assert rc == L.TDS_EINVAL
     assert lib.tds_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None) == L.TDS_OK
+
+
+def test_fetch_trajectories_arguments():
+    import ctypes as C
+    lib = L.lib()
+    n = C.c_int64(-1)
+    assert lib.tds_fetch_trajectories(None, None, L.TDS_MEM_HOST, None, 0, L.TDS_MEM_HOST,
+                                      C.byref(n)) == L.TDS_EINVAL
+    assert b"tds_fetch_trajectories" in lib.tds_last_error()

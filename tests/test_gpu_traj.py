@@ -1,0 +1,207 @@
+"""Trajectory-level answers and point queries on the GPU, against the oracle.
+
+* the device merge of a straight pass past a stationary point (both cut at
+  different times) is the one closed-form interval;
+* merged records equal the oracle's union of its own segment hits (pairs
+  identical, ends within the tolerance) on C1, reduced C2 and C4;
+* trajectory ids and output in device memory; caps; a batch without hits;
+* stationary query points (segments with equal end points) against straight
+  moving entries give the closed-form interval of |A + v (t - t0) - P| <= d.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+from gen import fixtures as fx
+from gen import workloads
+import oracle
+from oracle.trajectories import union_by_trajectory
+import paper_1405_7461_amd as tds
+from gpu_util import TOL, say
+
+pytestmark = pytest.mark.gpu
+MODES = ("fp32_refine", "fp64")
+
+
+def _traj(points, times, tid):
+    return workloads.from_polylines(np.asarray(points, dtype=np.float64)[None],
+                                    np.asarray(times, dtype=np.float64)[None], [tid])
+
+
+def _device_union(db, q, m, mode, **kw):
+    ix = tds.build_index(db, m)
+    qh = tds.Query(ix)
+    try:
+        qh.batch(q, q.d, mode=mode, tiling="range")
+        u = qh.fetch_trajectories(q.traj, **kw)
+    finally:
+        qh.close()
+        ix.close()
+    return u
+
+
+def _as_np(u):
+    f = (lambda a: a.cpu().numpy()) if hasattr(u.query_traj, "cpu") else np.asarray
+    return f(u.query_traj), f(u.entry_traj), f(u.ta), f(u.tb)
+
+
+def _compare(u, want, label):
+    qt, et, ta, tb = _as_np(u)
+    assert len(qt) == len(want), f"{label}: {len(qt)} merged intervals vs oracle {len(want)}"
+    assert np.array_equal(qt, want.qtraj) and np.array_equal(et, want.etraj), f"{label}: pairs differ"
+    for g, w in ((ta, want.ta), (tb, want.tb)):
+        err = np.abs(g - w) / np.maximum(1.0, np.abs(w))
+        assert err.size == 0 or err.max() <= TOL, f"{label}: end error {err.max()}"
+
+
+def _oracle_union(db, q):
+    h = oracle.search(db, q)
+    return union_by_trajectory(h.q, h.e, h.ta, h.tb, q.traj, db.traj), h
+
+
+def test_closed_form_across_boundaries():
+    d, h = 2.0, 0.75
+    ts = np.linspace(0.0, 20.0, 9)
+    xx = -10.0 + ts
+    q = _traj(np.column_stack([xx, np.full_like(xx, h), np.zeros_like(xx)]), ts, 11).with_d(d)
+    db = _traj([[0, 0, 0]] * 4, [0.0, 3.0, 9.5, 20.0], 7)
+    w = math.sqrt(d * d - h * h)
+    for mode in MODES:
+        u = _device_union(db, q, 4, mode)
+        qt, et, ta, tb = _as_np(u)
+        assert list(qt) == [11] and list(et) == [7], mode
+        assert abs(ta[0] - (10 - w)) <= 1e-9 * 10 and abs(tb[0] - (10 + w)) <= 1e-9 * 10, mode
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_union_matches_oracle(mode):
+    cases = [("C1", gen.make_config("C1"))]
+    db = gen.make_db("C2", ntraj=300)
+    qb = gen.make_queries("C2", nq=20)
+    cases.append(("C2r", (db, gen.concat([qb.with_d(x) for x in (1.0, 5.0, 25.0)]), 1000)))
+    cases.append(("C4r", (gen.make_db("C4", ntraj=300), gen.make_queries("C4", nq=24), 1000)))
+    db, q = fx.dense_box(ntraj=60, L=20, box=4.0, nq=8, seed=43, d=1.5)
+    cases.append(("dense", (db, q, 20)))
+    for label, (db, q, m) in cases:
+        want, h = _oracle_union(db, q)
+        say(f"{label} {mode}: {len(h)} segment hits -> {len(want)} trajectory intervals")
+        u = _device_union(db, q, m, mode)
+        _compare(u, want, f"{label} {mode}")
+
+
+def test_device_ids_output_and_cap():
+    import torch
+    db, q = fx.dense_box(ntraj=60, L=20, box=4.0, nq=8, seed=43, d=1.5)
+    want, _ = _oracle_union(db, q)
+    assert len(want) > 10
+    ix = tds.build_index(db, 20)
+    qh = tds.Query(ix)
+    try:
+        qh.batch(q, q.d, mode="fp32_refine", tiling="range")
+        u = qh.fetch_trajectories(torch.as_tensor(q.traj, device="cuda"), out="device")
+        torch.cuda.synchronize()
+        _compare(u, want, "device ids and output")
+        k = len(want) // 3
+        part = qh.fetch_trajectories(q.traj, cap=k)
+        qt, et, ta, tb = _as_np(part)
+        assert len(qt) == k and np.array_equal(qt, want.qtraj[:k]) and np.array_equal(et, want.etraj[:k])
+        # the segment-level fetch still works for the same batch
+        hits = qh.fetch().sorted()
+        assert len(hits) == len(oracle.search(db, q))
+        # a new batch holds no merge to copy until ids are given
+        import ctypes as C
+        from paper_1405_7461_amd import _lib as L
+        qh.batch(q, q.d, mode="fp32_refine", tiling="range")
+        n = C.c_int64()
+        rc = L.lib().tds_fetch_trajectories(qh._h, None, L.TDS_MEM_HOST, None, 0, L.TDS_MEM_HOST,
+                                            C.byref(n))
+        assert rc == L.TDS_ESTATE
+        assert len(qh.fetch_trajectories(q.traj)) == len(want)
+    finally:
+        qh.close()
+        ix.close()
+
+
+def test_batch_without_hits():
+    db = gen.make_db("C1", ntraj=30)
+    q = gen.make_queries("C1", nq=2).with_d(0.0)
+    q.x0 = q.x0 + 1e6
+    q.x1 = q.x1 + 1e6
+    u = _device_union(db, q, 100, "fp32_refine")
+    assert len(u) == 0
+
+
+def test_point_queries_closed_form():
+    # entries move straight from A to B over [0, 8]; query points sit still
+    rng = np.random.default_rng(5)
+    n_e = 64
+    a = rng.uniform(-5, 5, size=(n_e, 3))
+    b = a + rng.uniform(-4, 4, size=(n_e, 3))
+    db = fx.segments_from_rows(np.column_stack([a, np.zeros(n_e), b, np.full(n_e, 8.0)]))
+    p = rng.uniform(-3, 3, size=(16, 3))
+    pts = tds.point_segments(p[:, 0], p[:, 1], p[:, 2], np.full(16, 0.5), np.full(16, 7.5))
+    d = 3.0
+    ix = tds.build_index(db, 4)
+    qh = tds.Query(ix)
+    try:
+        for mode in MODES:
+            qh.batch(pts, np.full(16, d), mode=mode, tiling="range")
+            h = qh.fetch().sorted()
+            assert len(h) > 5
+            for qi, ei, ta, tb in zip(h.query, h.entry, h.ta, h.tb):
+                v = (b[ei] - a[ei]) / 8.0
+                w0 = a[ei] - p[qi]
+                # |w0 + v t|^2 <= d^2 on [0.5, 7.5]
+                A, B, Cc = v @ v, 2 * (w0 @ v), w0 @ w0 - d * d
+                disc = B * B - 4 * A * Cc
+                r1, r2 = (-B - math.sqrt(disc)) / (2 * A), (-B + math.sqrt(disc)) / (2 * A)
+                lo, hi = max(0.5, r1), min(7.5, r2)
+                assert abs(ta - lo) <= 1e-9 * max(1, abs(lo)) and abs(tb - hi) <= 1e-9 * max(1, abs(hi)), \
+                    (mode, qi, ei, ta, lo, tb, hi)
+    finally:
+        qh.close()
+        ix.close()
+
+
+def test_hit_dense_full_size():
+    # every one of the 2,500 database trajectories (400 segments over [0, 400])
+    # shifted by 0.5 in x and searched at d = 5: about a million segment hits.
+    # Each trajectory stays 0.5 from its own copy at all times, so its self
+    # pair is exactly one interval [0, 400]; all other pairs of 8 sampled query
+    # trajectories are compared with the oracle's union over the whole database.
+    db = gen.make_db("C2")
+    q = db.subset(np.arange(len(db))).with_d(5.0)
+    q.x0 = q.x0 + 0.5
+    q.x1 = q.x1 + 0.5
+    ix = tds.build_index(db, 1000)
+    qh = tds.Query(ix)
+    try:
+        qh.batch(q, q.d, mode="fp32_refine", tiling="range")
+        u = qh.fetch_trajectories(q.traj)
+        n_seg = qh.stats()["n_hit"]
+    finally:
+        qh.close()
+        ix.close()
+    say(f"hit-dense: {n_seg} segment hits -> {len(u)} trajectory intervals")
+    assert n_seg >= len(db)
+    qt, et, ta, tb = _as_np(u)
+    self_pair = qt == et
+    assert np.array_equal(np.sort(qt[self_pair]), np.arange(2500))
+    assert np.all(ta[self_pair] == 0.0) and np.all(tb[self_pair] == 400.0)
+    key = qt * 4096 + et
+    assert np.all(np.diff(key) >= 0)
+    rng = np.random.default_rng(77)
+    for t in rng.choice(2500, size=8, replace=False):
+        sub = q.subset(np.nonzero(q.traj == t)[0])
+        h = oracle.search(db, sub)
+        want = union_by_trajectory(h.q, h.e, h.ta, h.tb, sub.traj, db.traj)
+        sel = qt == t
+        got = TrajHitsView(qt[sel], et[sel], ta[sel], tb[sel])
+        _compare(got, want, f"hit-dense query trajectory {t}")
+
+
+class TrajHitsView:
+    def __init__(self, qt, et, ta, tb):
+        self.query_traj, self.entry_traj, self.ta, self.tb = qt, et, ta, tb
