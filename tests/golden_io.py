@@ -38,3 +38,11 @@ def fig2():
         elif tag == "total":
             totals[int(v[0])] = (int(v[1]), int(v[2]))
     return batches, totals
+
+
+def fig2_greedy():
+    rows = []
+    for tag, v in _rows("fig2_greedy.txt"):
+        if tag == "greedy":
+            rows.append((v[0], int(v[1]), [int(x) for x in v[2].split(",")], int(v[3])))
+    return rows
