@@ -224,8 +224,22 @@ def trajectory_form(ix, db, dq, q, opts, log_fn=log, steps=10, warmup=2):
     return out
 
 
+def _tiling_summary(trials):
+    """Fastest trial of each tiling (Periodic and GreedySetSplit over their sizes)."""
+    best = {}
+    for t in trials:
+        k = t.opts["tiling"]
+        if k not in best or t.ms < best[k].ms:
+            best[k] = t
+    return {k: dict(ms_per_step=round(t.ms, 4), pair_ms=round(t.pair_ms, 4), prep_ms=round(t.prep_ms, 4),
+                    n_eval=int(t.n_eval), n_tiles=int(t.n_tiles), num_bins=t.num_bins,
+                    batch_size=t.opts.get("batch_size"), block_size=t.opts["block_size"])
+            for k, t in best.items()}
+
+
 def batching_form(log_fn=log, reps=10):
-    """C4: uneven query set, per-query d, one persistent launch, autotuned."""
+    """C4: uneven query set, per-query d, one persistent launch, autotuned over
+    the tilings (range buckets, Periodic, GreedySetSplit-Min/-Max of Alg. 4)."""
     import torch
     import gen
     import paper_1405_7461_amd as tds
@@ -236,8 +250,8 @@ def batching_form(log_fn=log, reps=10):
     dq = to_device(q)
     t0 = time.perf_counter()
     res = tune(db, dq, dq.d, mode="fp32_refine", num_bins=(400, 1000, 2000),
-               tilings=("range",), blocks=(256, 1024), reps=2, use_cache=False,
-               cache=None)
+               tilings=("range", "periodic", "greedy_min", "greedy_max"), batch_sizes=(64, 256, 1024),
+               blocks=(256, 1024), reps=2, use_cache=False, cache=None)
     tune_s = time.perf_counter() - t0
     ix = tds.build_index(db, res.num_bins)
     r = run_form(ix, dq, res.opts, reps, 2, n_ovl)
@@ -246,8 +260,27 @@ def batching_form(log_fn=log, reps=10):
                         "log-uniform length 10-2000 (segments of 1/8), per-trajectory d in {1,5,25}",
                n_query_segments=len(q), n_overlap=n_ovl, tuned=dict(num_bins=res.num_bins, **res.opts),
                tune_s=round(tune_s, 2), trials=len(res.trials), value=r["value"], unit="pair-tests/s",
-               ms_per_step=r["ms_per_step"], pair_ms=r["pair_ms"], n_hit=r["n_hit"], n_eval=r["n_eval"])
+               ms_per_step=r["ms_per_step"], pair_ms=r["pair_ms"], n_hit=r["n_hit"], n_eval=r["n_eval"],
+               best_per_tiling=_tiling_summary(res.trials))
     log_fn(f"batching (C4): {out['value']:.4g} pair-tests/s, {out['ms_per_step']:.3f} ms/step, tuned {out['tuned']}")
+    for k, v in out["best_per_tiling"].items():
+        log_fn(f"  best {k}: {v}")
+    return out
+
+
+def tiling_comparison(ix, dq, n_ovl, log_fn=log, steps=10, warmup=2):
+    """The headline batch under each tiling at one launch shape."""
+    out = {}
+    for name, extra in (("range", {}), ("periodic", dict(batch_size=128)),
+                        ("greedy_min", dict(batch_size=256)), ("greedy_max", dict(batch_size=1024))):
+        opts = dict(mode="fp32_refine", tiling=name, block_size=256, **extra)
+        r = run_form(ix, dq, opts, steps, warmup, n_ovl)
+        out[name] = dict(batch_size=extra.get("batch_size"), ms_per_step=round(r["ms_per_step"], 4),
+                         pair_ms=round(r["pair_ms"], 4), prep_ms=round(r["prep_ms"], 4),
+                         n_eval=r["n_eval"], n_hit=r["n_hit"], value=r["value"])
+        log_fn(f"tiling {name}: {out[name]}")
+    hits = {v["n_hit"] for v in out.values()}
+    assert len(hits) == 1, out
     return out
 
 
@@ -328,6 +361,8 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-trajectories", action="store_true")
+    ap.add_argument("--no-tilings", action="store_true",
+                    help="skip the headline batch under the other tilings")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the forms, run a plain device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters)")
@@ -411,6 +446,8 @@ def main():
         "roofline": roof,
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "opts"} for k, v in results.items()},
     }
+    if not args.no_tilings:
+        line["tilings"] = tiling_comparison(ix, dq, n_ovl)
     if not args.no_trajectories:
         line["trajectories"] = trajectory_form(ix, db, dq, q, forms["fp32_refine"])
     if not args.no_batching:

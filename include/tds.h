@@ -88,6 +88,14 @@ typedef struct {
 /* How query segments are grouped into tiles (batches, Sec. 6). */
 #define TDS_TILE_PERIODIC 0     /* consecutive runs of batch_size segments in t_start order ("Periodic") */
 #define TDS_TILE_RANGE 1        /* runs of <= batch_size segments with the same candidate bin range */
+/* GreedySetSplit (Sec. 6, Alg. 4) over the query segments with candidates in
+ * (t_start, caller index) order: first every run of consecutive segments with
+ * the same candidate range becomes one batch (the merges that add no
+ * interactions), then a second pass merges each batch with its successor
+ * while the batch holds fewer than batch_size segments (Min), or while the
+ * merged batch would hold at most batch_size segments (Max). */
+#define TDS_TILE_GREEDY_MIN 2
+#define TDS_TILE_GREEDY_MAX 3
 
 /* Query flags. */
 #define TDS_QF_TIMING 1          /* record per-stage HIP event times (tds_stats.ms_*) */
@@ -97,7 +105,8 @@ typedef struct {
 typedef struct {
     int32_t mode;        /* TDS_MODE_* */
     int32_t tiling;      /* TDS_TILE_* */
-    int32_t batch_size;  /* TDS_TILE_PERIODIC: query segments per tile (s), 1..65536; 0 = 128 */
+    int32_t batch_size;  /* TDS_TILE_PERIODIC: query segments per tile (s); TDS_TILE_GREEDY_*:
+                            the bound; 1..65536; 0 = 128 */
     int32_t block_size;  /* pair-kernel threads per workgroup: 64, 128, 256, 512 or 1024; 0 = 256 */
     int32_t reserved0;   /* 0 */
     int32_t max_retries; /* result-buffer regrowths allowed; < 0 = 4 */
@@ -227,6 +236,28 @@ int tds_query_stats(const tds_query *qh, tds_stats *out);
 /* After tds_fetch_results: the candidate range the device computed for each
  * query segment of the last batch (caller order, host arrays of n values). */
 int tds_query_ranges(const tds_query *qh, int64_t *first, int64_t *last, int64_t n);
+
+/* One tile (batch) of the last batch's pair launch. */
+typedef struct {
+    int32_t q_first; /* first member: position in the member order of tds_query_tiles */
+    int32_t n_query; /* member query segments (positions q_first .. q_first + n_query - 1) */
+    int32_t e_first; /* candidate range: entries e_first .. e_first + n_entry - 1 of the index,
+                        counted in the index's t_start order (ties in caller order) */
+    int32_t n_entry;
+} tds_tile_info; /* 16 bytes */
+
+/*
+ * After tds_fetch_results (or tds_fetch_trajectories): the tiles (batches,
+ * Sec. 6) the device built for the last batch and the order of their
+ * members. Writes min(cap, n_tiles) tiles to `tiles` and min(member_cap,
+ * n_members) caller indices of query segments to `members` (host memory;
+ * either pointer may be NULL with a cap of 0); *n_tiles and *n_members
+ * receive the totals. Query segments without candidates are in no tile.
+ * Errors: TDS_EINVAL for null counts or a negative cap, a null array with a
+ * positive cap; TDS_ESTATE before a fetched batch; TDS_EDEVICE on a failed copy.
+ */
+int tds_query_tiles(const tds_query *qh, tds_tile_info *tiles, int64_t cap, int32_t *members,
+                    int64_t member_cap, int64_t *n_tiles, int64_t *n_members);
 
 /*
  * Trajectory-level answer of the last batch (Sec. 3: per query trajectory,

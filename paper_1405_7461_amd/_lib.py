@@ -25,6 +25,8 @@ TDS_MODE_FP64 = 0
 TDS_MODE_FP32_REFINE = 1
 TDS_TILE_PERIODIC = 0
 TDS_TILE_RANGE = 1
+TDS_TILE_GREEDY_MIN = 2
+TDS_TILE_GREEDY_MAX = 3
 TDS_QF_TIMING = 1
 TDS_QF_COUNT_OVERLAP = 2
 TDS_QF_KERNEL_OVERLAP = 4
@@ -57,6 +59,11 @@ class tds_hit(C.Structure):
 class tds_traj_hit(C.Structure):
     _fields_ = [("query_traj", C.c_int64), ("entry_traj", C.c_int64), ("t_a", C.c_double),
                 ("t_b", C.c_double)]
+
+
+class tds_tile_info(C.Structure):
+    _fields_ = [("q_first", C.c_int32), ("n_query", C.c_int32), ("e_first", C.c_int32),
+                ("n_entry", C.c_int32)]
 
 
 class tds_stats(C.Structure):
@@ -99,6 +106,8 @@ SIGNATURES = {
     "tds_fetch_trajectories": (C.c_int, [_P, _P, C.c_int32, _P, C.c_int64, C.c_int32,
                                          C.POINTER(C.c_int64)]),
     "tds_query_ranges": (C.c_int, [_P, _P, _P, C.c_int64]),
+    "tds_query_tiles": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]),
     "tds_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "tds_last_error": (C.c_char_p, []),
     "tds_abi_version": (C.c_int, []),

@@ -16,7 +16,8 @@ from . import _lib as L
 
 FIELDS = ("x0", "y0", "z0", "t0", "x1", "y1", "z1", "t1")
 MODES = {"fp64": L.TDS_MODE_FP64, "fp32_refine": L.TDS_MODE_FP32_REFINE}
-TILINGS = {"periodic": L.TDS_TILE_PERIODIC, "range": L.TDS_TILE_RANGE}
+TILINGS = {"periodic": L.TDS_TILE_PERIODIC, "range": L.TDS_TILE_RANGE,
+           "greedy_min": L.TDS_TILE_GREEDY_MIN, "greedy_max": L.TDS_TILE_GREEDY_MAX}
 
 
 def _is_torch(x) -> bool:
@@ -303,6 +304,22 @@ class Query:
         s = L.tds_stats()
         L.check(L.lib().tds_query_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in L.tds_stats._fields_}
+
+    def tiles(self):
+        """Tiles of the last fetched batch and the caller indices in tile order.
+
+        Returns (tiles, members): tiles is a structured array with fields
+        q_first, n_query, e_first, n_entry (q_first indexes members).
+        """
+        nt, nm = C.c_int64(), C.c_int64()
+        L.check(L.lib().tds_query_tiles(self._h, None, 0, None, 0, C.byref(nt), C.byref(nm)))
+        dt = np.dtype([("q_first", np.int32), ("n_query", np.int32), ("e_first", np.int32),
+                       ("n_entry", np.int32)])
+        tiles = np.zeros(max(nt.value, 1), dtype=dt)
+        members = np.zeros(max(nm.value, 1), dtype=np.int32)
+        L.check(L.lib().tds_query_tiles(self._h, tiles.ctypes.data, nt.value, members.ctypes.data,
+                                        nm.value, C.byref(nt), C.byref(nm)))
+        return tiles[: nt.value], members[: nm.value]
 
     def ranges(self):
         first = np.empty(max(self._nq, 1), np.int64)

@@ -6,8 +6,10 @@ configuration runs the same query batch, the fastest wins, and all of them
 must report the same number of hits (the hit set does not depend on launch
 shape, so a mismatch is an error, not a tuning result).
 
-Searched: bin count m (rebuilds the index), tiling (range buckets or the
-paper's Periodic batches), batch size s for Periodic, and workgroup size.
+Searched: bin count m (rebuilds the index), tiling (range buckets, the
+paper's Periodic batches, or its GreedySetSplit-Min / -Max batches of
+Alg. 4), the batch size s of Periodic or the bound of GreedySetSplit, and
+the workgroup size.
 Results are cached in a JSON file keyed by the workload's shape.
 """
 from __future__ import annotations
@@ -35,6 +37,8 @@ class Trial:
     pair_ms: float
     n_hit: int
     n_eval: int
+    prep_ms: float = 0.0   # query preparation, sort and tiling (HIP events)
+    n_tiles: int = 0
 
 
 @dataclass
@@ -58,7 +62,7 @@ def workload_key(n_entries: int, n_queries: int, d, mode: str) -> str:
 
 def _time_config(qh, q, d, opts, reps, stream):
     import torch
-    best_ms, best_pair, hits, n_eval = np.inf, np.inf, None, None
+    best_ms, best_pair, best_prep, hits, n_eval, n_tiles = np.inf, np.inf, np.inf, None, None, 0
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -69,12 +73,14 @@ def _time_config(qh, q, d, opts, reps, stream):
         st = qh.stats()
         best_ms = min(best_ms, ms)
         best_pair = min(best_pair, st["ms_pair"])
-        hits, n_eval = len(h), st["n_eval"]
-    return best_ms, best_pair, hits, n_eval
+        best_prep = min(best_prep, st["ms_prep"])
+        hits, n_eval, n_tiles = len(h), st["n_eval"], st["n_tiles"]
+    return best_ms, best_pair, best_prep, hits, n_eval, n_tiles
 
 
 def tune(db, q, d, mode: str = "fp32_refine", num_bins: Sequence[int] = (250, 500, 1000, 2000, 4000),
-         tilings: Sequence[str] = ("range", "periodic"), batch_sizes: Sequence[int] = (64, 128, 256),
+         tilings: Sequence[str] = ("range", "periodic", "greedy_min", "greedy_max"),
+         batch_sizes: Sequence[int] = (64, 128, 256),
          blocks: Sequence[int] = (64, 256, 1024),
          reps: int = 3, cache: Optional[Path] = DEFAULT_CACHE, use_cache: bool = True,
          log=None) -> TuneResult:
@@ -101,18 +107,20 @@ def tune(db, q, d, mode: str = "fp32_refine", num_bins: Sequence[int] = (250, 50
         qh = api.Query(ix)
         try:
             for tiling, blk in itertools.product(tilings, blocks):
-                for bs in (batch_sizes if tiling == "periodic" else (0,)):
+                for bs in (batch_sizes if tiling != "range" else (0,)):
                     opts = dict(mode=mode, tiling=tiling, block_size=blk)
                     if bs:
                         opts["batch_size"] = bs
-                    ms, pair_ms, hits, n_eval = _time_config(qh, q, d, opts, reps, stream)
+                    ms, pair_ms, prep_ms, hits, n_eval, n_tiles = _time_config(qh, q, d, opts, reps,
+                                                                                stream)
                     if ref_hits is None:
                         ref_hits = hits
                     if hits != ref_hits:
                         raise RuntimeError(f"hit count {hits} != {ref_hits} for m={m} {opts}")
-                    trials.append(Trial(m, opts, ms, pair_ms, hits, n_eval))
+                    trials.append(Trial(m, opts, ms, pair_ms, hits, n_eval, prep_ms, n_tiles))
                     if log:
-                        log(f"m={m} {opts}: {ms:.3f} ms (pair {pair_ms:.3f}), N_eval {n_eval}")
+                        log(f"m={m} {opts}: {ms:.3f} ms (pair {pair_ms:.3f}, prep {prep_ms:.3f}), "
+                            f"N_eval {n_eval}, tiles {n_tiles}")
         finally:
             qh.close()
             ix.close()

@@ -23,7 +23,7 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{ROOT / 'include'}",
 ]
-SOURCES = ["tds_kernels.hip", "tds_traj.hip", "tds_api.cpp"]
+SOURCES = ["tds_kernels.hip", "tds_traj.hip", "tds_greedy.hip", "tds_api.cpp"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: Path | None = None) -> Path:

@@ -168,6 +168,7 @@ struct tds_query {
     DBuf qrank, bcount, bj2, bq_off, tiles, units, unit_off, ctr;
     DBuf qstage, cand, hits, slab_n, slab_h, hit_off, wave_ovl, out_stage;
     DBuf tr_qtraj, tr_work, tr_temp, tr_out;  // trajectory merge
+    DBuf gs_work, gs_jump;                     // GreedySetSplit tiling
     Slabs sl{};                    // slab view of the buffers above
     long long nslabs_alloc = 0;    // slabs the cand / hits buffers hold
     int32_t nwaves_alloc = 0;      // wave slabs slab_n / wave_ovl hold
@@ -177,6 +178,7 @@ struct tds_query {
     tds_query_opts opts{};
     int block = 256, grid = 0;
     bool pending = false, fetched = false;
+    int64_t n_sorted = 0;     // query segments placed in tiles (last fetched batch)
     bool traj_valid = false;  // tr_out holds the merged records of this batch
     long long traj_total = 0;
     tds_stats stats{};
@@ -470,7 +472,8 @@ void tds_query_destroy(tds_query *q) {
                     &q->last_s, &q->key, &q->perm, &q->qrank, &q->bcount, &q->bj2, &q->bq_off,
                     &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
                     &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage,
-                    &q->tr_qtraj, &q->tr_work, &q->tr_temp, &q->tr_out})
+                    &q->tr_qtraj, &q->tr_work, &q->tr_temp, &q->tr_out, &q->gs_work,
+                    &q->gs_jump})
         b->release();
     if (q->host_ctr) (void)hipHostFree(q->host_ctr);
     for (auto &ev : q->ev)
@@ -501,6 +504,37 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
         HIP_TRY(q->bj2.ensure(n * 4));
         q->cap_buckets = nbuckets;
     }
+    return TDS_OK;
+}
+
+// Work arrays of the GreedySetSplit tiling of nq query segments. The batch
+// chain is marked with `levels` doubling passes, enough for 2^levels - 1
+// batches: with Min every batch but the last holds at least `bound`
+// segments, with Max two neighbouring batches hold more than `bound`.
+static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, GreedyBufs *g) {
+    const long long most = is_max ? 2LL * nq / ((long long)bound + 1) + 2 : (long long)nq / bound + 2;
+    int levels = 1;
+    while ((1LL << levels) <= most) ++levels;
+    const size_t n = (size_t)nq, n1 = n + 1;
+    // 8-byte arrays first: kin, tev; then the 4-byte ones, then the flags
+    const size_t n16 = (n + 15) & ~(size_t)15;
+    const size_t bytes = n * 8 * 2 + n * 4 + n1 * 4 * 3 + 2 * 4 + n16 + 64;
+    HIP_TRY(q->gs_work.ensure(bytes));
+    HIP_TRY(q->gs_jump.ensure((size_t)levels * n1 * 4));
+    char *w = q->gs_work.as<char>();
+    auto take = [&](size_t b) { char *p = w; w += b; return p; };
+    g->kin = (unsigned long long *)take(n * 8);
+    g->tev = (long long *)take(n * 8);
+    g->vout = (int32_t *)take(n * 4);
+    g->gpos = (int32_t *)take(n1 * 4);
+    g->mark = (int32_t *)take(n1 * 4);
+    g->gb = (int32_t *)take(n1 * 4);
+    g->cnt = (int32_t *)take(2 * 4);
+    w = (char *)(((uintptr_t)w + 15) & ~(uintptr_t)15);
+    g->flag = (uint8_t *)take(n16);
+    g->jump = q->gs_jump.as<int32_t>();
+    g->stride = (int32_t)n1;
+    g->levels = levels;
     return TDS_OK;
 }
 
@@ -568,7 +602,8 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     tds_query_opts o = *opts;
     if (o.mode != TDS_MODE_FP64 && o.mode != TDS_MODE_FP32_REFINE)
         return fail(TDS_EINVAL, "tds_query_batch: unknown mode %d", o.mode);
-    if (o.tiling != TDS_TILE_PERIODIC && o.tiling != TDS_TILE_RANGE)
+    if (o.tiling != TDS_TILE_PERIODIC && o.tiling != TDS_TILE_RANGE &&
+        o.tiling != TDS_TILE_GREEDY_MIN && o.tiling != TDS_TILE_GREEDY_MAX)
         return fail(TDS_EINVAL, "tds_query_batch: unknown tiling %d", o.tiling);
     if (o.batch_size == 0) o.batch_size = 128;
     if (o.batch_size < 1 || o.batch_size > 65536)
@@ -651,9 +686,18 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.unit_off = q->unit_off.as<long long>();
     b.ctr = q->ctr.as<Counters>();
 
+    const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
+    GreedyBufs gb{};
+    if (greedy && nq > 0) {
+        rc = greedy_buffers(q, nq, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, &gb);
+        if (rc) return rc;
+    }
+
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
     if (timing) HIP_TRY(hipEventRecord(q->ev[0], st));
     HIP_TRY(launch_prepare(qin, din, b, ix->dev, st));
+    if (greedy && nq > 0)
+        HIP_TRY(launch_greedy(b, gb, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, st));
     rc = launch_search(q);
     if (rc) return rc;
     q->pending = true;
@@ -705,6 +749,7 @@ static int complete_batch(tds_query *q, const char *who) {
         s.n_refine = (int64_t)c.cand;
         s.n_hit = (int64_t)c.hits;
         s.n_tiles = (int64_t)c.n_tiles;
+        q->n_sorted = (int64_t)c.n_sorted;
         s.n_items = (int64_t)c.n_units;
         s.grid = q->grid;
         s.retries = retries;
@@ -837,6 +882,31 @@ int tds_query_stats(const tds_query *q, tds_stats *out) {
     if (!q || !out) return fail(TDS_EINVAL, "tds_query_stats: null argument");
     if (!q->fetched) return fail(TDS_ESTATE, "tds_query_stats: no fetched batch");
     *out = q->stats;
+    return TDS_OK;
+}
+
+int tds_query_tiles(const tds_query *q, tds_tile_info *tiles, int64_t cap, int32_t *members,
+                    int64_t member_cap, int64_t *n_tiles, int64_t *n_members) {
+    if (!q || !n_tiles || !n_members || cap < 0 || member_cap < 0 || (cap > 0 && !tiles) ||
+        (member_cap > 0 && !members))
+        return fail(TDS_EINVAL, "tds_query_tiles: invalid argument");
+    if (!q->fetched) return fail(TDS_ESTATE, "tds_query_tiles: no fetched batch");
+    *n_tiles = q->stats.n_tiles;
+    *n_members = q->n_sorted;
+    const int64_t nt = std::min<int64_t>(cap, q->stats.n_tiles);
+    if (nt > 0) {
+        std::vector<Tile> t((size_t)nt);
+        HIP_TRY(hipMemcpy(t.data(), q->tiles.p, (size_t)nt * sizeof(Tile), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < nt; ++k) {
+            tiles[k].q_first = t[k].q0;
+            tiles[k].n_query = t[k].nq;
+            tiles[k].e_first = t[k].e0;
+            tiles[k].n_entry = t[k].ne;
+        }
+    }
+    const int64_t nm = std::min<int64_t>(member_cap, q->n_sorted);
+    if (nm > 0)
+        HIP_TRY(hipMemcpy(members, q->perm.p, (size_t)nm * 4, hipMemcpyDeviceToHost));
     return TDS_OK;
 }
 

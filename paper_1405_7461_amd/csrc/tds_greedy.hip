@@ -1,0 +1,363 @@
+// GreedySetSplit tiles (Sec. 6, Alg. 4) built on the device.
+//
+// The algorithm walks the query segments in t_start order twice. Its first
+// pass merges neighbours while the merge adds no interactions; since a
+// batch costs (its segments) x (entries of its candidate range) and a merged
+// range is the hull of the two, a merge is free exactly when the two ranges
+// are identical, so the first pass yields the maximal runs of consecutive
+// segments with identical ranges ("groups"), found from one flag per
+// position.
+//
+// The second pass is sequential in the paper: a batch takes the following
+// groups while it holds fewer than `bound` segments (Min), or while the
+// merged batch stays within `bound` (Max). Which group starts the batch
+// after a batch starting at group g depends only on g (next(g), a binary
+// search over the group start positions), so the batch starts are the chain
+// 0, next(0), next(next(0)), ... It is marked in parallel by pointer
+// doubling: jump_k(g) = next^(2^k)(g) for k < L, then top down the chain
+// nodes at multiples of 2^k are the ones at multiples of 2^(k+1) and their
+// jump_k images. L levels cover chains of fewer than 2^L batches.
+//
+// Launches: the exact (t_start, caller index) order within each t_start bin
+// (the query preparation's counting sort already orders the bins), with a
+// fallback for bins too large for LDS; placement of the sorted order with
+// the run flags; one workgroup for groups, chain and batch starts (in LDS
+// when there are fewer than kChainLds groups); the tiles; one workgroup for
+// the unit offsets.
+#include <hip/hip_runtime.h>
+
+#include "tds_internal.h"
+
+namespace tds {
+
+namespace {
+
+__device__ __forceinline__ unsigned long long start_bits(double x) {
+    x = x + 0.0;  // -0 sorts with +0
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Exact (t_start, caller index) order within each t_start bin (the bins
+// are already in order: the counting sort of the query preparation put the
+// segments of bin k at bq_off[k] .. bq_off[k] + bcount[k] - 1 of perm, in
+// no particular order). One workgroup per bin: up to kSortLds segments are
+// sorted in LDS by a bitonic network on (order bits of t_start, caller
+// index), a unique key; larger bins only get their keys written in bin order
+// for k_gs_rank_big.
+constexpr int kSortBlock = 256;
+constexpr int kSortLds = 4096;
+
+__global__ __launch_bounds__(kSortBlock) void k_gs_bin_sort(DevBatch b, GreedyBufs g) {
+    __shared__ unsigned long long s_key[kSortLds];
+    __shared__ int32_t s_idx[kSortLds];
+    const int k = blockIdx.x;
+    if (k >= b.nbuckets) return;
+    const int cnt = b.bcount[k];
+    if (cnt <= 0) return;
+    const int off = b.bq_off[k];
+    const int tid = threadIdx.x;
+    if (cnt > kSortLds) {
+        for (int p = tid; p < cnt; p += kSortBlock) g.kin[off + p] = start_bits(b.rec[b.perm[off + p]].t0);
+        return;
+    }
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int p = tid; p < P; p += kSortBlock) {
+        if (p < cnt) {
+            const int i = b.perm[off + p];
+            s_key[p] = start_bits(b.rec[i].t0);
+            s_idx[p] = i;
+        } else {  // padding sorts last
+            s_key[p] = ~0ull;
+            s_idx[p] = 0x7fffffff;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int p = tid; p < P; p += kSortBlock) {
+                const int l = p ^ stride;
+                if (l > p) {
+                    const unsigned long long ka = s_key[p], kb = s_key[l];
+                    const int ia = s_idx[p], ib = s_idx[l];
+                    const bool a_gt = ka > kb || (ka == kb && ia > ib);
+                    const bool up = (p & size) == 0;
+                    if (a_gt == up) {  // out of order for this direction
+                        s_key[p] = kb;
+                        s_key[l] = ka;
+                        s_idx[p] = ib;
+                        s_idx[l] = ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int p = tid; p < cnt; p += kSortBlock) g.vout[off + p] = s_idx[p];
+}
+
+// Bins of more than kSortLds segments: each segment's position in its bin is
+// the number of bin members with a smaller (t_start, caller index) key,
+// counted over the keys k_gs_bin_sort wrote (quadratic in the bin size, but
+// only for bins too large for LDS).
+__global__ void k_gs_rank_big(DevBatch b, GreedyBufs g) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int)b.ctr->n_sorted) return;
+    const int i = b.perm[p];
+    const int k = b.key[i];
+    const int cnt = b.bcount[k];
+    if (cnt <= kSortLds) return;
+    const int off = b.bq_off[k];
+    const unsigned long long mine = g.kin[p];
+    int rank = 0;
+    for (int q = off; q < off + cnt; ++q) {
+        const unsigned long long o = g.kin[q];
+        rank += (o < mine || (o == mine && b.perm[q] < i)) ? 1 : 0;
+    }
+    g.vout[off + rank] = i;
+}
+
+// Sorted order -> perm, sorted ranges, run-start flags (one byte per
+// position; positions past the segments with candidates, up to the next
+// multiple of 16, get 0).
+__global__ void k_gs_place(DevBatch b, GreedyBufs g, int n16) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n16) return;
+    const int nv = (int)b.ctr->n_sorted;
+    uint8_t flag = 0;
+    if (p < nv) {
+        const int i = g.vout[p];
+        const int f = b.first[i], l = b.last[i];
+        b.perm[p] = i;
+        b.first_s[p] = f;
+        b.last_s[p] = l;
+        flag = 1;
+        if (p > 0) {
+            const int j = g.vout[p - 1];
+            flag = (f != b.first[j] || l != b.last[j]) ? 1 : 0;
+        }
+    }
+    g.flag[p] = flag;
+}
+
+constexpr int kChainBlock = 1024;
+constexpr int kChainLds = 1024;     // groups + 1 held in LDS
+constexpr int kChainLdsLevels = 10; // 2^10 > any chain of fewer than kChainLds groups
+
+// Exclusive scan of one value per thread over the block; the block total
+// goes to *total.
+__device__ long long gs_block_scan(long long v, long long *total) {
+    __shared__ long long sums[kChainBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    long long incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) sums[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        long long s = lane < kChainBlock / 64 ? sums[lane] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(s, off);
+            if (lane >= off) s += y;
+        }
+        if (lane < kChainBlock / 64) sums[lane] = s;
+    }
+    __syncthreads();
+    const long long before = w > 0 ? sums[w - 1] : 0;
+    *total = sums[kChainBlock / 64 - 1];
+    __syncthreads();
+    return before + incl - v;
+}
+
+__device__ __forceinline__ int flag_count(const uint4 v) {
+    return __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);  // bytes are 0 or 1
+}
+
+// One workgroup: groups (run starts), next(), the doubling levels, the
+// chain marks and the batch starts. Writes gpos, gb and cnt to global memory.
+__global__ __launch_bounds__(kChainBlock) void k_gs_chain(DevBatch b, GreedyBufs g, int bound,
+                                                          int is_max) {
+    __shared__ int32_t s_gpos[kChainLds];
+    __shared__ int32_t s_mark[kChainLds];
+    __shared__ int32_t s_jump[kChainLdsLevels * kChainLds];
+    const int tid = threadIdx.x;
+    const int nv = (int)b.ctr->n_sorted;
+
+    // groups: each thread counts the flags of a run of 16-byte words
+    const int nw = (nv + 15) >> 4;
+    const int per = (nw + kChainBlock - 1) / kChainBlock;
+    const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
+    const uint4 *fw = reinterpret_cast<const uint4 *>(g.flag);
+    long long c = 0;
+    for (int k = w0; k < w1; ++k) c += flag_count(fw[k]);
+    long long gtot;
+    long long base = gs_block_scan(c, &gtot);
+    const int G = (int)gtot;
+    const bool lds = G + 1 <= kChainLds;
+    int32_t *gp = lds ? s_gpos : g.gpos;
+    int32_t *jp = lds ? s_jump : g.jump;
+    int32_t *mk = lds ? s_mark : g.mark;
+    const size_t stride = lds ? (size_t)kChainLds : (size_t)g.stride;
+    for (int k = w0; k < w1; ++k) {
+        const uint4 v = fw[k];
+        const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((words[q] >> (8 * j)) & 0xffu) gp[base++] = k * 16 + q * 4 + j;
+    }
+    if (tid == 0) gp[G] = nv;
+    __syncthreads();
+
+    // levels: 2^L > G >= chain length (the global buffer holds g.levels)
+    int L = 1;
+    while ((1 << L) <= G) ++L;
+    if (!lds) L = min(L, g.levels);
+
+    for (int x = tid; x <= G; x += kChainBlock) {
+        int h = G;
+        if (x < G) {
+            const long long target = (long long)gp[x] + bound;
+            if (!is_max) {  // smallest h > x with gpos[h] >= gpos[x] + bound, else G
+                int lo = x + 1, hi = G;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((long long)gp[mid] >= target) hi = mid; else lo = mid + 1;
+                }
+                h = lo;
+            } else {  // largest h with gpos[h] <= gpos[x] + bound, at least x + 1
+                int lo = x + 1, hi = G + 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if ((long long)gp[mid] > target) hi = mid; else lo = mid + 1;
+                }
+                h = max(x + 1, lo - 1);
+            }
+        }
+        jp[x] = h;
+        mk[x] = (x == 0 && G > 0) ? L : -1;
+    }
+    __syncthreads();
+    for (int k = 1; k < L; ++k) {  // jump_k = jump_{k-1} o jump_{k-1}
+        const int32_t *prev = jp + (size_t)(k - 1) * stride;
+        int32_t *cur = jp + (size_t)k * stride;
+        for (int x = tid; x <= G; x += kChainBlock) cur[x] = prev[prev[x]];
+        __syncthreads();
+    }
+    // Chain nodes found above level k map to the nodes 2^k further on; a
+    // node marked at level k is not a source at level k, so no thread of a
+    // level reads a mark another thread of the same level writes.
+    for (int k = L - 1; k >= 0; --k) {
+        const int32_t *jk = jp + (size_t)k * stride;
+        for (int x = tid; x < G; x += kChainBlock) {
+            if (mk[x] > k) {
+                const int y = jk[x];
+                if (y < G) mk[y] = k;
+            }
+        }
+        __syncthreads();
+    }
+
+    // batch starts: the marked groups, numbered in order
+    const int perg = (G + kChainBlock - 1) / kChainBlock;
+    const int x0 = min(G, tid * perg), x1 = min(G, x0 + perg);
+    long long nb_loc = 0;
+    for (int x = x0; x < x1; ++x) nb_loc += mk[x] >= 0 ? 1 : 0;
+    long long nbt;
+    long long bpos = gs_block_scan(nb_loc, &nbt);
+    for (int x = x0; x < x1; ++x)
+        if (mk[x] >= 0) g.gb[bpos++] = x;
+    if (lds)
+        for (int x = tid; x <= G; x += kChainBlock) g.gpos[x] = s_gpos[x];
+    if (tid == 0) {
+        g.gb[nbt] = G;
+        g.cnt[0] = G;
+        g.cnt[1] = (int)nbt;
+    }
+}
+
+// Tiles, one wave at a time (grid-stride over the batches): the members are
+// the groups gb[t] .. gb[t+1]-1, the range is the hull of their (within a
+// group identical) ranges.
+constexpr int kTileGrid = 1024;
+
+__global__ void k_gs_tiles(DevBatch b, GreedyBufs g) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+    const int nb = g.cnt[1];
+    for (int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); t < nb; t += nwaves) {
+        const int g0 = g.gb[t], g1 = g.gb[t + 1];
+        int lo = 0x7fffffff, hi = -1;
+        for (int k = g0 + lane; k < g1; k += 64) {
+            const int p = g.gpos[k];
+            lo = min(lo, b.first_s[p]);
+            hi = max(hi, b.last_s[p]);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        if (lane == 0) {
+            const int q0 = g.gpos[g0], nq = g.gpos[g1] - q0;
+            Tile tl;
+            tl.q0 = q0;
+            tl.nq = nq;
+            tl.e0 = lo;
+            tl.ne = hi - lo + 1;
+            tl.nchunk = (tl.ne + b.chunk - 1) / b.chunk;
+            tl.echunk = chunk_entries(tl.ne, tl.nchunk);
+            tl.pad0 = tl.pad1 = 0;
+            b.tiles[t] = tl;
+            b.units[t] = (long long)tl.nchunk * nq;
+            g.tev[t] = (long long)nq * tl.ne;
+        }
+    }
+}
+
+// One block: unit offsets of the tiles, the tile count, the work units and
+// the interactions (n_eval).
+__global__ __launch_bounds__(kChainBlock) void k_gs_unit_scan(DevBatch b, GreedyBufs g) {
+    const int n = g.cnt[1];
+    const int per = (n + kChainBlock - 1) / kChainBlock;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    long long s = 0, ev = 0;
+    for (int k = lo; k < hi; ++k) {
+        s += b.units[k];
+        ev += g.tev[k];
+    }
+    long long tot, ev_tot;
+    long long run = gs_block_scan(s, &tot);
+    (void)gs_block_scan(ev, &ev_tot);
+    for (int k = lo; k < hi; ++k) {
+        b.unit_off[k] = run;
+        run += b.units[k];
+    }
+    if (threadIdx.x == 0) {
+        b.unit_off[n] = tot;
+        b.ctr->n_tiles = (unsigned)n;
+        b.ctr->n_units = (unsigned long long)tot;
+        b.ctr->n_eval = (unsigned long long)ev_tot;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_greedy(DevBatch b, GreedyBufs g, int bound, int is_max, hipStream_t st) {
+    const int nq = b.nq;
+    if (nq <= 0) return hipErrorInvalidValue;  // the caller skips an empty batch
+    const int blk = 256;
+    const int n16 = (nq + 15) & ~15;
+    hipLaunchKernelGGL(k_gs_bin_sort, dim3(b.nbuckets), dim3(kSortBlock), 0, st, b, g);
+    hipLaunchKernelGGL(k_gs_rank_big, dim3((nq + blk - 1) / blk), dim3(blk), 0, st, b, g);
+    hipLaunchKernelGGL(k_gs_place, dim3((n16 + blk - 1) / blk), dim3(blk), 0, st, b, g, n16);
+    hipLaunchKernelGGL(k_gs_chain, dim3(1), dim3(kChainBlock), 0, st, b, g, bound, is_max);
+    hipLaunchKernelGGL(k_gs_tiles, dim3(kTileGrid), dim3(blk), 0, st, b, g);
+    hipLaunchKernelGGL(k_gs_unit_scan, dim3(1), dim3(kChainBlock), 0, st, b, g);
+    return hipGetLastError();
+}
+
+}  // namespace tds

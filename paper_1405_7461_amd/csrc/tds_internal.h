@@ -156,7 +156,22 @@ struct TrajBufs {
 };
 
 enum : int { kModeFP64 = 0, kModeFP32Refine = 1 };
-enum : int { kTilePeriodic = 0, kTileRange = 1 };
+enum : int { kTilePeriodic = 0, kTileRange = 1, kTileGreedyMin = 2, kTileGreedyMax = 3 };
+
+// Work arrays of the GreedySetSplit tiling (nq = query segments of the batch).
+struct GreedyBufs {
+    unsigned long long *kin;         // t_start order bits, bin order (large bins) [nq]
+    int32_t *vout;                   // caller indices in (t_start, caller index) order [nq]
+    uint8_t *flag;                   // run start by sorted position [nq rounded up to 16]
+    int32_t *gpos;                   // first sorted position of each run (group) [nq + 1]
+    int32_t *jump;                   // levels x stride: the 2^k-th next batch start
+    int32_t *mark;                   // level at which a group was found a batch start [nq + 1]
+    int32_t *gb;                     // first group of each batch [nq + 1]
+    long long *tev;                  // interactions of each tile [nq]
+    int32_t *cnt;                    // [0] groups, [1] batches
+    int32_t stride;                  // nq + 1
+    int32_t levels;                  // doubling levels the jump buffer holds
+};
 
 // Launchers (tds_kernels.hip). All enqueue on `st`, return hipError_t.
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
@@ -179,6 +194,10 @@ hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
 // Trajectory merge (tds_traj.hip): temp bytes for n hits, and the launch
 // (n > 0 hits; writes the merged records to `out` and their number to *total).
 size_t traj_temp_bytes(long long n);
+// GreedySetSplit tiles (after launch_prepare with a greedy tiling): orders
+// the query segments with candidates, builds the runs, the batch chain and
+// the tiles, and scans the work units.
+hipError_t launch_greedy(DevBatch b, GreedyBufs g, int bound, int is_max, hipStream_t st);
 hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
                              const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,
                              size_t temp_bytes, tds_traj_hit *out, long long *total,

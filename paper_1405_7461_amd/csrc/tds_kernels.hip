@@ -271,7 +271,7 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
                 key = j1 * kSpanClasses + cls;
                 if (cls == kSpanClasses - 1) atomicMax(&b.bj2[key], j2);
             }
-        } else {
+        } else if (b.tiling == kTilePeriodic || any) {  // greedy: segments with candidates
             double u = floor((s0 - ix.t_first) / ix.width);
             key = u <= 0.0 ? 0 : (u >= (double)(b.nbuckets - 1) ? b.nbuckets - 1 : (int)u);
         }

@@ -148,3 +148,12 @@ def test_fetch_trajectories_arguments():
     assert lib.tds_fetch_trajectories(None, None, L.TDS_MEM_HOST, None, 0, L.TDS_MEM_HOST,
                                       C.byref(n)) == L.TDS_EINVAL
     assert b"tds_fetch_trajectories" in lib.tds_last_error()
+
+
+def test_query_tiles_arguments():
+    import ctypes as C
+    lib = L.lib()
+    assert C.sizeof(L.tds_tile_info) == 16
+    a, b = C.c_int64(), C.c_int64()
+    assert lib.tds_query_tiles(None, None, 0, None, 0, C.byref(a), C.byref(b)) == L.TDS_EINVAL
+    assert b"tds_query_tiles" in lib.tds_last_error()

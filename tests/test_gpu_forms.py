@@ -61,7 +61,10 @@ def test_autotune_consistent(tmp_path):
     q = gen.make_queries("C4", nq=20)
     res = tune(db, q, q.d, num_bins=(200, 800), blocks=(64, 256), batch_sizes=(64, 256), reps=1,
                cache=tmp_path / "tune.json", log=say)
-    assert len(res.trials) == 2 * (2 + 2 * 2)
+    # per bin count and block size: range, then Periodic, GreedySetSplit-Min
+    # and -Max at each of the two sizes
+    assert len(res.trials) == 2 * 2 * (1 + 3 * 2)
+    assert {t.opts["tiling"] for t in res.trials} == {"range", "periodic", "greedy_min", "greedy_max"}
     assert (tmp_path / "tune.json").exists()
     got, st, _ = run(db, q, res.num_bins, **res.opts)
     compare(got, oracle.search(db, q), db, "tuned")
