@@ -284,6 +284,64 @@ def tiling_comparison(ix, dq, n_ovl, log_fn=log, steps=10, warmup=2):
     return out
 
 
+def model_form(log_fn=log, steps=8, warmup=2):
+    """Sec. 8's response-time model re-fitted here: calibration, alpha per
+    epoch from a representative query set, predicted against measured times
+    for the headline batch and for Periodic batch sizes (the paper's Table 3:
+    the model's choice of s against the measured best)."""
+    import gen
+    from gen import workloads as W
+    import paper_1405_7461_amd as tds
+    from paper_1405_7461_amd import perfmodel as M
+    t0 = time.perf_counter()
+    model = M.calibrate(qs=(64, 1024, 16384, 131072), cs=(256, 1024, 4096, 16384, 65536), reps=3,
+                        max_hits=1 << 24)
+    cal_s = time.perf_counter() - t0
+    out = dict(calibration_s=round(cal_s, 2), cpu_fit=dict(model.cpu.__dict__), scenarios={})
+    sizes = (32, 64, 128, 256, 512, 1024)
+    for name in ("C2", "C4"):
+        db = gen.make_db(name)
+        if name == "C2":
+            q = gen.concat([gen.make_queries("C2").with_d(d) for d in D_VALUES])
+            rep0 = W.gaussian_walk(W.rng_for(2, 7), 20, 400, 1000.0, 1.0)
+            rep = gen.concat([rep0.with_d(d) for d in D_VALUES])
+        else:
+            q = gen.make_queries("C4")
+            rng = W.rng_for(4, 7)
+            rep = W.short_queries(rng, 64, 10, 2000, 1.0 / 8, 1.0 / 64, 400.0, 1000.0, "exp", 1.0 / 8)
+            rep = rep.with_d(W.rng_for(4, 8).choice(np.asarray(D_VALUES), size=64)[rep.traj])
+        n_ovl = overlap_count(db, q)
+        ix = tds.build_index(db, NUM_BINS)
+        est = M.estimate_alpha(model, ix, rep, num_epochs=50, s=256)
+        dq = to_device(q)
+        rows = []
+        for tiling, s in [("range", 0)] + [("periodic", s) for s in sizes]:
+            opts = dict(mode="fp32_refine", tiling=tiling, block_size=256)
+            if s:
+                opts["batch_size"] = s
+            r = run_form(ix, dq, opts, steps, warmup, n_ovl)
+            p = model.predict(ix, q, tiling=tiling, batch_size=s or 128)
+            rows.append(dict(tiling=tiling, s=s or None, measured_ms=round(r["ms_per_step"], 4),
+                             predicted_ms=round(p["ms"], 4),
+                             rel_error=round(p["ms"] / r["ms_per_step"] - 1, 3),
+                             interactions_model=p["interactions"], interactions_device=r["n_eval"],
+                             alpha=p["alpha"], beta=p["beta"]))
+        ix.close()
+        per = [x for x in rows if x["tiling"] == "periodic"]
+        chosen = min(per, key=lambda x: x["predicted_ms"])
+        best = min(per, key=lambda x: x["measured_ms"])
+        out["scenarios"][name] = dict(
+            alpha_estimate=est, rows=rows, model_s=chosen["s"], actual_s=best["s"],
+            slowdown=round(chosen["measured_ms"] / best["measured_ms"] - 1, 4),
+            mean_abs_rel_error=round(float(np.mean([abs(x["rel_error"]) for x in rows])), 3))
+        log_fn(f"model {name}: alpha {est}, model s {chosen['s']}, actual s {best['s']}, slowdown "
+               f"{out['scenarios'][name]['slowdown']:.2%}, mean |error| "
+               f"{out['scenarios'][name]['mean_abs_rel_error']:.1%}")
+        for x in rows:
+            log_fn(f"  {x}")
+    return out
+
+
 def serving_form(log_fn=log, n_requests=400, rates=(0.5, 0.8, 0.95)):
     """C5: 10M-segment resident index, Poisson request arrivals at 3 rates."""
     import gen
@@ -361,6 +419,8 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-trajectories", action="store_true")
+    ap.add_argument("--no-model", action="store_true",
+                    help="skip the response-time model (calibration and predictions)")
     ap.add_argument("--no-tilings", action="store_true",
                     help="skip the headline batch under the other tilings")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -452,6 +512,8 @@ def main():
         line["trajectories"] = trajectory_form(ix, db, dq, q, forms["fp32_refine"])
     if not args.no_batching:
         line["batching"] = batching_form()
+    if not args.no_model:
+        line["model"] = model_form()
     if not args.no_serving:
         line["serving"] = serving_form()
     if not args.no_cpu_baseline:

@@ -184,6 +184,14 @@ int tds_index_info_get(const tds_index *ix, tds_index_info *out);
 /* Copy up to cap non-empty bins (in time order) to host memory; *n_out gets
  * their number. */
 int tds_index_bins(const tds_index *ix, tds_bin *out, int64_t cap, int64_t *n_out);
+/* Copy the index's t_start values (in its t_start order) and its t_end values
+ * (sorted on their own) to host arrays of n values, n = the entry count.
+ * With them the number of entries whose span overlaps an interval (a, b)
+ * with positive length is count(t_start < b) - count(t_end <= a), two binary
+ * searches (the exact temporal-miss count of Sec. 8's beta). Errors:
+ * TDS_EINVAL for null arrays with n > 0 or n other than the entry count,
+ * TDS_EDEVICE on a failed copy. */
+int tds_index_times(const tds_index *ix, double *t_start_sorted, double *t_end_sorted, int64_t n);
 /* Release the index. Every query handle made from it must be destroyed first. */
 void tds_index_destroy(tds_index *ix);
 

@@ -106,6 +106,7 @@ SIGNATURES = {
     "tds_fetch_trajectories": (C.c_int, [_P, _P, C.c_int32, _P, C.c_int64, C.c_int32,
                                          C.POINTER(C.c_int64)]),
     "tds_query_ranges": (C.c_int, [_P, _P, _P, C.c_int64]),
+    "tds_index_times": (C.c_int, [_P, _P, _P, C.c_int64]),
     "tds_query_tiles": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64)]),
     "tds_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),

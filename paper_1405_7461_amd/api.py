@@ -124,6 +124,16 @@ class Index:
         L.check(L.lib().tds_index_bins(self._h, out, n.value, C.byref(n)))
         return _bins_array(out, n.value)
 
+    def sorted_times(self):
+        """(t_start in the index's order, t_end sorted on its own), host arrays."""
+        if getattr(self, "_times", None) is None:
+            n = int(self.info()["n"])
+            a = np.empty(max(n, 1), np.float64)
+            b = np.empty(max(n, 1), np.float64)
+            L.check(L.lib().tds_index_times(self._h, a.ctypes.data, b.ctypes.data, n))
+            self._times = (a[:n], b[:n])
+        return self._times
+
     def close(self):
         if self._h:
             L.lib().tds_index_destroy(self._h)

@@ -434,6 +434,16 @@ int tds_index_bins(const tds_index *ix, tds_bin *out, int64_t cap, int64_t *n_ou
     return TDS_OK;
 }
 
+int tds_index_times(const tds_index *ix, double *t_start_sorted, double *t_end_sorted, int64_t n) {
+    if (!ix || (n > 0 && (!t_start_sorted || !t_end_sorted)))
+        return fail(TDS_EINVAL, "tds_index_times: null argument");
+    if (n != ix->n) return fail(TDS_EINVAL, "tds_index_times: n must equal the entry count");
+    if (n == 0) return TDS_OK;
+    HIP_TRY(hipMemcpy(t_start_sorted, ix->t0.p, (size_t)n * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t_end_sorted, ix->t1s.p, (size_t)n * 8, hipMemcpyDeviceToHost));
+    return TDS_OK;
+}
+
 void tds_index_destroy(tds_index *ix) {
     if (!ix) return;
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,

@@ -137,6 +137,8 @@ __global__ void k_zero_batch(DevBatch b) {
 
 // Bin tables up to this size (16 bytes per bin) are staged in LDS by k_qprep.
 constexpr int kQprepLdsBins = 2048;
+// Groups of lanes with a common bucket that k_qprep ranks with one atomic each.
+constexpr int kRankGroups = 4;
 
 // First index k in [0, nb) with a[k] > x (a non-decreasing), nb if none.
 __device__ __forceinline__ int first_greater(const double *a, int nb, double x) {
@@ -195,6 +197,7 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         __syncthreads();
     }
     unsigned long long novl = 0;
+    int key = -1, kj2 = -1;  // bucket, and the last bin for the open span class
     if (i < b.nq) {
         bool ok = isfinite(a0) && isfinite(b0) && isfinite(c0) && isfinite(s0) && isfinite(a1) &&
                   isfinite(b1) && isfinite(c1) && isfinite(s1) && isfinite(d) && d >= 0.0 &&
@@ -264,19 +267,53 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         if (b.count_overlap && ok)
             novl = (unsigned long long)(count_less(ix.t0, ix.n, s1) - count_leq(ix.t1s, ix.n, s0));
 
-        int key = -1;
         if (b.tiling == kTileRange) {
             if (any) {
                 int cls = min(j2 - j1, kSpanClasses - 1);
                 key = j1 * kSpanClasses + cls;
-                if (cls == kSpanClasses - 1) atomicMax(&b.bj2[key], j2);
+                if (cls == kSpanClasses - 1) kj2 = j2;
             }
         } else if (b.tiling == kTilePeriodic || any) {  // greedy: segments with candidates
             double u = floor((s0 - ix.t_first) / ix.width);
             key = u <= 0.0 ? 0 : (u >= (double)(b.nbuckets - 1) ? b.nbuckets - 1 : (int)u);
         }
-        b.qrank[i] = key >= 0 ? atomicAdd(&b.bcount[key * kBucketSub + (i % kBucketSub)], 1) : 0;
         b.key[i] = key;
+    }
+    // Rank within the bucket. Returning atomics on one address serialize, so
+    // lanes of a wave that share a bucket (up to kRankGroups groups, most
+    // often all of them) take their ranks with one atomic per group; the rest
+    // take one each. The open span class's last bin goes up the same way.
+    static_assert(kBucketSub == 1, "grouped ranks assume one counter per bucket");
+    {
+        const int lane = (int)lane_id();
+        bool done = key < 0;
+        int rank = 0;
+        for (int it = 0; it < kRankGroups; ++it) {
+            const unsigned long long act = __ballot(!done);
+            if (act == 0ull) break;
+            const int leader = __ffsll((long long)act) - 1;
+            const int kl = __shfl(key, leader);
+            const bool mine = !done && key == kl;
+            const unsigned long long m = __ballot(mine);
+            int jm = mine ? kj2 : -1;  // the group's largest last bin
+            for (int off = 32; off > 0; off >>= 1) jm = max(jm, __shfl_xor(jm, off));
+            int base = 0;
+            if (lane == leader) {
+                base = atomicAdd(&b.bcount[kl], __popcll(m));
+                if (jm >= 0) atomicMax(&b.bj2[kl], jm);
+            }
+            base = __shfl(base, leader);
+            if (mine) {
+                rank = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                done = true;
+            }
+        }
+        if (!done) {
+            rank = atomicAdd(&b.bcount[key], 1);
+            if (kj2 >= 0) atomicMax(&b.bj2[key], kj2);
+        }
+        if (i < b.nq) b.qrank[i] = key >= 0 ? rank : 0;
     }
     novl = wave_sum_u64(novl);
     if (lane_id() == 0 && novl) atomicAdd(&b.ctr->n_overlap_exact, novl);
