@@ -120,7 +120,9 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
     for i in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        qh.batch(prep, None, timing=True, stream=stream, **opts)
+        # HIP events on the pair kernel's dispatch (the lightest timing); the
+        # event times are read after the step
+        qh.batch(prep, None, timing="pair", stream=stream, **opts)
         h = qh.fetch(out="device")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -130,6 +132,14 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
             pair_ms.append(st["ms_pair"])
             stats = st
             n_hit = len(h)
+    # stage breakdown from a few more steps with every stage timed
+    prep_ms, refine_ms = [], []
+    for i in range(3):
+        qh.batch(prep, None, timing=True, stream=stream, **opts)
+        qh.fetch(out="device")
+        st = qh.stats()
+        prep_ms.append(st["ms_prep"])
+        refine_ms.append(st["ms_refine"])
     qh.close()
     lat = np.array(lat)
     ms = float(lat.mean() * 1e3)
@@ -137,8 +147,8 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pair_ms=float(np.mean(pair_ms)),
                 n_hit=int(n_hit), n_eval=int(stats["n_eval"]), n_overlap=int(counted),
                 n_refine=int(stats["n_refine"]), retries=int(stats["retries"]),
-                n_items=int(stats["n_items"]), grid=int(stats["grid"]), prep_ms=float(stats["ms_prep"]),
-                opts=opts)
+                n_items=int(stats["n_items"]), grid=int(stats["grid"]), prep_ms=float(np.median(prep_ms)),
+                refine_ms=float(np.median(refine_ms)), opts=opts)
 
 
 def cpu_baseline(db, q, n_ovl_total, target_s=10.0):

@@ -98,9 +98,11 @@ typedef struct {
 #define TDS_TILE_GREEDY_MAX 3
 
 /* Query flags. */
-#define TDS_QF_TIMING 1          /* record per-stage HIP event times (tds_stats.ms_*) */
+#define TDS_QF_TIMING 1          /* record per-stage HIP event times; tds_query_stats reads them */
 #define TDS_QF_COUNT_OVERLAP 2   /* count pairs whose spans overlap (tds_stats.n_overlap) */
 #define TDS_QF_KERNEL_OVERLAP 4  /* the pair kernel also counts the overlapping pairs it examined */
+#define TDS_QF_TIMING_PAIR 8     /* time only the pair kernel (tds_stats.ms_pair; the other ms_* are 0):
+                                    two events on one dispatch, the lightest timing */
 
 typedef struct {
     int32_t mode;        /* TDS_MODE_* */
@@ -236,8 +238,8 @@ int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
  * indices and write min(cap, n) records to `out` (host memory when out_mem is
  * TDS_MEM_HOST, device memory for TDS_MEM_DEVICE). *n_total always receives
  * the number of hits, so cap = 0 sizes the buffer. Host output is complete on
- * return; device output is written on the batch's stream (complete on return
- * only with TDS_QF_TIMING), so work on another stream must wait for it.
+ * return; device output is written on the batch's stream, so work on another
+ * stream must wait for it.
  */
 int tds_fetch_results(tds_query *qh, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total);
 int tds_query_stats(const tds_query *qh, tds_stats *out);

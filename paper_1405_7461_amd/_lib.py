@@ -30,6 +30,7 @@ TDS_TILE_GREEDY_MAX = 3
 TDS_QF_TIMING = 1
 TDS_QF_COUNT_OVERLAP = 2
 TDS_QF_KERNEL_OVERLAP = 4
+TDS_QF_TIMING_PAIR = 8
 
 _P = C.c_void_p
 

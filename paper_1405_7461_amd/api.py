@@ -225,13 +225,16 @@ class Query:
         self._keep = None
         self._nq = 0
         self._stream = None
+        self._rows_hint = 1024  # output rows for the next fetch
 
     def batch(self, q, d, mode="fp64", tiling="periodic", batch_size=0, block_size=0,
               capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False,
               kernel_overlap=False, stream=None):
         p = q if isinstance(q, Prepared) else Prepared(q, d)
         s, dptr, keep = p.segments, p.dptr, p.keep
-        flags = ((L.TDS_QF_TIMING if timing else 0) | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
+        # timing: True records every stage, "pair" only the pair kernel
+        tflag = L.TDS_QF_TIMING_PAIR if timing == "pair" else (L.TDS_QF_TIMING if timing else 0)
+        flags = (tflag | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
                  | (L.TDS_QF_KERNEL_OVERLAP if kernel_overlap else 0))
         o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,
                              int(max_retries), int(capacity), int(grid), flags)
@@ -242,17 +245,29 @@ class Query:
         return self
 
     def fetch(self, out: str = "host", cap: Optional[int] = None) -> Hits:
+        """Results of the last batch. The output buffer is sized from the
+        previous batch's hit count, so one library call usually suffices; a
+        larger result is fetched again into a buffer of its size."""
         n = C.c_int64()
-        L.check(L.lib().tds_fetch_results(self._h, None, 0, L.TDS_MEM_HOST, C.byref(n)))
-        total = int(n.value)
-        m = total if cap is None else min(int(cap), total)
+        rows = max(self._rows_hint, 1) if cap is None else max(int(cap), 1)
         if out == "device":
             import torch
-            buf = torch.empty((max(m, 1), 5), dtype=torch.int64, device="cuda")
-            if m:
-                L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(buf.data_ptr()), m,
-                                                  L.TDS_MEM_DEVICE, C.byref(n)))
-                # the records are written on the batch's stream
+            mk = lambda r: torch.empty((r, 5), dtype=torch.int64, device="cuda")
+            ptr, mem = (lambda b: b.data_ptr()), L.TDS_MEM_DEVICE
+        else:
+            mk = lambda r: np.empty((r, 5), dtype=np.int64)
+            ptr, mem = (lambda b: b.ctypes.data), L.TDS_MEM_HOST
+        buf = mk(rows)
+        L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(ptr(buf)), rows, mem, C.byref(n)))
+        total = int(n.value)
+        m = total if cap is None else min(int(cap), total)
+        if m > rows:
+            buf = mk(m)
+            L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(ptr(buf)), m, mem, C.byref(n)))
+        self._rows_hint = max(1024, total + total // 4)
+        if out == "device":
+            import torch
+            if m:  # the records are written on the batch's stream
                 qs = self._stream
                 if qs is not None and not isinstance(qs, int) and qs != torch.cuda.current_stream():
                     torch.cuda.current_stream().wait_stream(qs)
@@ -260,11 +275,7 @@ class Query:
             res = Hits(buf[:, 0], buf[:, 1], buf[:, 2], buf[:, 3].view(torch.float64),
                        buf[:, 4].view(torch.float64))
         else:
-            arr = np.empty((max(m, 1), 5), dtype=np.int64)
-            if m:
-                L.check(L.lib().tds_fetch_results(self._h, C.c_void_p(arr.ctypes.data), m,
-                                                  L.TDS_MEM_HOST, C.byref(n)))
-            arr = arr[:m]
+            arr = buf[:m]
             res = Hits(arr[:, 0].copy(), arr[:, 1].copy(), arr[:, 2].copy(),
                        arr[:, 3].copy().view(np.float64), arr[:, 4].copy().view(np.float64))
         self._keep = None

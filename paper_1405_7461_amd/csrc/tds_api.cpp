@@ -179,6 +179,7 @@ struct tds_query {
     int block = 256, grid = 0;
     bool pending = false, fetched = false;
     int64_t n_sorted = 0;     // query segments placed in tiles (last fetched batch)
+    bool fetch_timed = false; // ev[4], ev[5] bracket the last fetch's translation
     bool traj_valid = false;  // tr_out holds the merged records of this batch
     long long traj_total = 0;
     tds_stats stats{};
@@ -589,12 +590,12 @@ static unsigned long long spill_capacity(const Slabs &sl) {
 static int launch_search(tds_query *q) {
     const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
     const int kovl = (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
-    if (timing) HIP_TRY(hipEventRecord(q->ev[1], q->stream));
+    // timing: events attached to the pair kernel's dispatch (start, end) and
+    // to the end of the hit scan
+    const bool tpair = timing || (q->opts.flags & TDS_QF_TIMING_PAIR) != 0;
     HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->opts.grid, kovl, q->sl,
-                        q->stream));
-    if (timing) HIP_TRY(hipEventRecord(q->ev[2], q->stream));
-    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream));
-    if (timing) HIP_TRY(hipEventRecord(q->ev[3], q->stream));
+                        q->stream, tpair ? q->ev[1] : nullptr, tpair ? q->ev[2] : nullptr));
+    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream, timing ? q->ev[3] : nullptr));
     HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
                            q->stream));
     return TDS_OK;
@@ -704,8 +705,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     }
 
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
-    if (timing) HIP_TRY(hipEventRecord(q->ev[0], st));
-    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st));
+    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st, timing ? q->ev[0] : nullptr));
     if (greedy && nq > 0)
         HIP_TRY(launch_greedy(b, gb, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, st));
     rc = launch_search(q);
@@ -763,11 +763,8 @@ static int complete_batch(tds_query *q, const char *who) {
         s.n_items = (int64_t)c.n_units;
         s.grid = q->grid;
         s.retries = retries;
-        if (q->opts.flags & TDS_QF_TIMING) {
-            HIP_TRY(hipEventElapsedTime(&s.ms_prep, q->ev[0], q->ev[1]));
-            HIP_TRY(hipEventElapsedTime(&s.ms_pair, q->ev[1], q->ev[2]));
-            HIP_TRY(hipEventElapsedTime(&s.ms_refine, q->ev[2], q->ev[3]));
-        }
+        // timing: the event times are read by tds_query_stats, outside the batch's path
+        q->fetch_timed = false;
         q->pending = false;
         q->fetched = true;
     }
@@ -801,10 +798,10 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
                                    hipMemcpyDeviceToHost, st));
         }
         if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
-        // device output is ordered on the batch's stream; host output and
-        // timing need the copy finished
-        if (timing || out_mem == TDS_MEM_HOST) HIP_TRY(hipStreamSynchronize(st));
-        if (timing) HIP_TRY(hipEventElapsedTime(&q->stats.ms_fetch, q->ev[4], q->ev[5]));
+        // device output is ordered on the batch's stream; host output needs
+        // the copy finished (fetch timing is read by tds_query_stats)
+        if (out_mem == TDS_MEM_HOST) HIP_TRY(hipStreamSynchronize(st));
+        if (timing) q->fetch_timed = true;
     }
     return TDS_OK;
 }
@@ -892,6 +889,17 @@ int tds_query_stats(const tds_query *q, tds_stats *out) {
     if (!q || !out) return fail(TDS_EINVAL, "tds_query_stats: null argument");
     if (!q->fetched) return fail(TDS_ESTATE, "tds_query_stats: no fetched batch");
     *out = q->stats;
+    // events of the last batch (complete after its fetch)
+    if (q->opts.flags & (TDS_QF_TIMING | TDS_QF_TIMING_PAIR))
+        HIP_TRY(hipEventElapsedTime(&out->ms_pair, q->ev[1], q->ev[2]));
+    if (q->opts.flags & TDS_QF_TIMING) {
+        HIP_TRY(hipEventElapsedTime(&out->ms_prep, q->ev[0], q->ev[1]));
+        HIP_TRY(hipEventElapsedTime(&out->ms_refine, q->ev[2], q->ev[3]));
+        if (q->fetch_timed) {
+            HIP_TRY(hipEventSynchronize(q->ev[5]));
+            HIP_TRY(hipEventElapsedTime(&out->ms_fetch, q->ev[4], q->ev[5]));
+        }
+    }
     return TDS_OK;
 }
 

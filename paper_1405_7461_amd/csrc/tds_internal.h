@@ -178,15 +178,19 @@ hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *per
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
                          double *z0, double *vx, double *vy, double *vz, float4 *ecen,
                          float2 *ehalf, int32_t *orig, int64_t *traj, hipStream_t st);
+// ev_start (optional) records the start of the first kernel.
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
-                          hipStream_t st);
+                          hipStream_t st, hipEvent_t ev_start = nullptr);
 // Workgroups of the pair launch: `grid` when > 0, else one per resident slot
 // (persistent launch). Slabs.nwaves must be pair_grid(...) * block / 64.
 int pair_grid(int mode, int block, int grid, int kernel_overlap);
+// ev0 / ev1 (optional) record the start and the end of the pair kernel.
 hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int kernel_overlap,
-                       Slabs sl, hipStream_t st);
-// Refine the selected pairs into hit slabs, then scan the hit counts.
-hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st);
+                       Slabs sl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Refine the selected pairs into hit slabs, then scan the hit counts;
+// ev_stop (optional) records the end of the scan.
+hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
+                         hipEvent_t ev_stop = nullptr);
 // Dense caller-index records of the first n hits.
 hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
                             DevIndex ix, void *out_hits, hipStream_t st);

@@ -20,9 +20,23 @@
 //         || (B < 0 && fma(a,T,B) > 0 && fma(B,B,-(a*c)) >= 0)
 // Built with -ffp-contract=off: every fma is explicit, nothing is fused or
 // reassociated behind the source's back.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "tds_internal.h"
+
+
+// Launch with optional start / stop events attached to the dispatch itself
+// (hipExtLaunchKernelGGL), which adds no packets to the stream; a separate
+// hipEventRecord around each kernel measured about 5 us per event here.
+#define TDS_LAUNCH_EV(start, stop, kernel, grid, block, shm, st, ...)                          \
+    do {                                                                                     \
+        if ((start) || (stop))                                                               \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, st, start, stop, 0, __VA_ARGS__); \
+        else                                                                                 \
+            hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                   \
+    } while (0)
 
 namespace tds {
 
@@ -545,11 +559,11 @@ __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
 }
 
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
-                          hipStream_t st) {
+                          hipStream_t st, hipEvent_t ev_start) {
     const int blk = 256;
     int zgrid = (b.nbuckets + blk - 1) / blk;
     zgrid = zgrid < 1 ? 1 : (zgrid > 1024 ? 1024 : zgrid);
-    hipLaunchKernelGGL(k_zero_batch, dim3(zgrid), dim3(blk), 0, st, b);
+    TDS_LAUNCH_EV(ev_start, nullptr, k_zero_batch, dim3(zgrid), dim3(blk), 0, st, b);
     if (b.nq == 0) TDS_LAUNCH_CHECK();
     const int qgrid = (b.nq + blk - 1) / blk;
     const size_t lds = ix.nb <= kQprepLdsBins ? (size_t)ix.nb * 2 * sizeof(double) : 0;
@@ -1088,25 +1102,29 @@ int pair_grid(int mode, int block, int grid, int kernel_overlap) {
 
 template <int MODE, int BLOCK>
 static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int kernel_overlap, Slabs sl,
-                                hipStream_t st) {
+                                hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     constexpr int EPT = ept_for_mode(MODE);
     const int g = pair_grid_b<MODE, BLOCK>(grid, kernel_overlap);
     if ((long long)g * (BLOCK / 64) != sl.nwaves || sl.nslabs <= sl.nwaves)
         return hipErrorInvalidValue;  // slabs sized for another launch
     if (kernel_overlap)
-        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, true>), dim3(g), dim3(BLOCK), 0, st, b.rec,
-                           b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
+        TDS_LAUNCH_EV(ev0, ev1, (k_pair<MODE, BLOCK, EPT, true>), dim3(g), dim3(BLOCK), 0, st,
+                      b.rec, b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
     else
-        hipLaunchKernelGGL((k_pair<MODE, BLOCK, EPT, false>), dim3(g), dim3(BLOCK), 0, st, b.rec,
-                           b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
+        TDS_LAUNCH_EV(ev0, ev1, (k_pair<MODE, BLOCK, EPT, false>), dim3(g), dim3(BLOCK), 0, st,
+                      b.rec, b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
     TDS_LAUNCH_CHECK();
 }
 
 hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, int kernel_overlap,
-                       Slabs sl, hipStream_t st) {
-    if (b.nq == 0) return hipSuccess;
+                       Slabs sl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (b.nq == 0) {  // nothing to launch: the events still mark the point
+        if (ev0) (void)hipEventRecord(ev0, st);
+        if (ev1) (void)hipEventRecord(ev1, st);
+        return hipGetLastError();
+    }
 #define TDS_PAIR_CASE(M, BS) \
-    case BS: return launch_pair_b<M, BS>(b, ix, grid, kernel_overlap, sl, st);
+    case BS: return launch_pair_b<M, BS>(b, ix, grid, kernel_overlap, sl, st, ev0, ev1);
     if (mode == kModeFP64) {
         switch (block) {
             TDS_PAIR_CASE(kModeFP64, 64)
@@ -1128,11 +1146,16 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st) {
-    if (b.nq == 0) return hipSuccess;
+hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
+                         hipEvent_t ev_stop) {
+    if (b.nq == 0) {
+        if (ev_stop) (void)hipEventRecord(ev_stop, st);
+        return hipGetLastError();
+    }
     static const int grid = resident_blocks(k_refine, 256);
     hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix, b.ctr);
-    hipLaunchKernelGGL(k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr, count_ovl);
+    TDS_LAUNCH_EV(nullptr, ev_stop, k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr,
+                  count_ovl);
     TDS_LAUNCH_CHECK();
 }
 
@@ -1162,9 +1185,10 @@ __global__ __launch_bounds__(256) void k_translate(Slabs sl, const Counters *__r
     const int lane = threadIdx.x & 63;
     const long long nsl = (long long)ctr->n_slabs;
     const long long nw = (long long)gridDim.x * 4;
+    const long long lim = min((long long)n, (long long)ctr->hits);  // n: the caller's capacity
     for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
         const long long k = sl.hit_off[s] + lane;
-        if (lane < sl.slab_h[s] && k < n) {
+        if (lane < sl.slab_h[s] && k < lim) {
             const Hit24 h = sl.hits[s * kSlab + lane];
             int64_t *o = out + 5 * k;
             o[0] = perm[h.q];
