@@ -595,9 +595,13 @@ static int launch_search(tds_query *q) {
     const bool tpair = timing || (q->opts.flags & TDS_QF_TIMING_PAIR) != 0;
     HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->opts.grid, kovl, q->sl,
                         q->stream, tpair ? q->ev[1] : nullptr, tpair ? q->ev[2] : nullptr));
-    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream, timing ? q->ev[3] : nullptr));
-    HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
-                           q->stream));
+    // the scan kernel writes the final counters to host_ctr itself; a batch
+    // without query segments launches no scan, so its counters are copied
+    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream, timing ? q->ev[3] : nullptr,
+                          q->host_ctr));
+    if (q->b.nq == 0)
+        HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
+                               q->stream));
     return TDS_OK;
 }
 

@@ -189,8 +189,9 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
                        Slabs sl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Refine the selected pairs into hit slabs, then scan the hit counts;
 // ev_stop (optional) records the end of the scan.
+// host_out (optional): pinned host copy of the final counters, written by the scan.
 hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
-                         hipEvent_t ev_stop = nullptr);
+                         hipEvent_t ev_stop = nullptr, Counters *host_out = nullptr);
 // Dense caller-index records of the first n hits.
 hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
                             DevIndex ix, void *out_hits, hipStream_t st);

@@ -309,6 +309,8 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
             const int kl = __shfl(key, leader);
             const bool mine = !done && key == kl;
             const unsigned long long m = __ballot(mine);
+            // a lone lane: the keys of this wave differ, one atomic each is as cheap
+            if (__popcll(m) == 1 && it == 0) break;
             int jm = mine ? kj2 : -1;  // the group's largest last bin
             for (int off = 32; off > 0; off >>= 1) jm = max(jm, __shfl_xor(jm, off));
             int base = 0;
@@ -989,8 +991,10 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
 // the whole kernel), longer ones in a loop.
 constexpr int kScanRun = 8;
 
+// The final counters also go to `host_out` (pinned host memory that the host
+// reads after the stream is synchronized), which saves a copy on the stream.
 __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
-                                                         int count_ovl) {
+                                                         int count_ovl, Counters *host_out) {
     const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
     const long long per = (nsl + kScanBlock - 1) / kScanBlock;
     const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
@@ -1042,6 +1046,7 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
         ctr->cand = (unsigned long long)sel_tot;
         ctr->n_slabs = (unsigned long long)nsl;
         if (count_ovl) ctr->overlap = (unsigned long long)ovl_tot;
+        if (host_out) *host_out = *ctr;
     }
 }
 
@@ -1147,7 +1152,7 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
 }
 
 hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
-                         hipEvent_t ev_stop) {
+                         hipEvent_t ev_stop, Counters *host_out) {
     if (b.nq == 0) {
         if (ev_stop) (void)hipEventRecord(ev_stop, st);
         return hipGetLastError();
@@ -1155,7 +1160,7 @@ hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipSt
     static const int grid = resident_blocks(k_refine, 256);
     hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix, b.ctr);
     TDS_LAUNCH_EV(nullptr, ev_stop, k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr,
-                  count_ovl);
+                  count_ovl, host_out);
     TDS_LAUNCH_CHECK();
 }
 

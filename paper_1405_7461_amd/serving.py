@@ -157,6 +157,11 @@ class Server:
                 self.plan(r)
                 cap = int(r.est_bytes / HIT_BYTES) + 1024
                 ex(r.seg, np.broadcast_to(r.d, (r.n,)).astype(np.float64), cap)
+            # one batch of all of them with the whole pool as capacity: the
+            # device buffers reach the sizes the largest admitted batch needs
+            if requests:
+                seg, d = _concat(list(requests))
+                ex(seg, d, int(self.pool_bytes / HIT_BYTES) + 1024)
         self.batches.clear()
 
     def run(self, requests: Sequence[Request], time_scale: float = 1.0) -> Dict:
