@@ -783,28 +783,52 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
         return fail(TDS_EINVAL, "tds_fetch_results: bad out_mem");
     if (!q->pending && !q->fetched) return fail(TDS_ESTATE, "tds_fetch_results: no batch");
     hipStream_t st = q->stream;
+    const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
+    // A pending batch: the translation is enqueued before the host waits (it
+    // reads the hit count on the device and writes at most cap records), so
+    // the device does not idle while the host wakes up. It is redone below
+    // if the batch had to be re-run or holds more hits than cap.
+    // Host output is staged on the device first; the early translation only
+    // uses staging that is already large enough (a generous cap allocates
+    // nothing before the count is known).
+    bool early = false;
+    const bool stage_fits = (size_t)cap * sizeof(tds_hit) <= q->out_stage.bytes;
+    if (q->pending && cap > 0 && (out_mem == TDS_MEM_DEVICE || stage_fits)) {
+        if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
+        if (out_mem == TDS_MEM_DEVICE)
+            HIP_TRY(launch_translate(q->sl, q->b.ctr, cap, q->b.perm, q->ix->dev, out, st));
+        else
+            HIP_TRY(launch_translate(q->sl, q->b.ctr, cap, q->b.perm, q->ix->dev, q->out_stage.p,
+                                     st));
+        if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
+        early = true;
+    }
     if (q->pending) {
         int rc = complete_batch(q, "tds_fetch_results");
         if (rc) return rc;
     }
-    int64_t n = q->stats.n_hit;
+    const int64_t n = q->stats.n_hit;
     *n_total = n;
-    int64_t m = std::min<int64_t>(cap, n);
+    const int64_t m = std::min<int64_t>(cap, n);
     if (m > 0) {
-        bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
-        if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
-        if (out_mem == TDS_MEM_DEVICE) {
-            HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, out, st));
-        } else {
-            HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
-            HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, q->out_stage.p, st));
+        if (!early || q->stats.retries > 0) {  // translate now
+            if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
+            if (out_mem == TDS_MEM_DEVICE) {
+                HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, out, st));
+            } else {
+                HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
+                HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, q->out_stage.p,
+                                         st));
+            }
+            if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
+        }
+        if (out_mem == TDS_MEM_HOST) {
             HIP_TRY(hipMemcpyAsync(out, q->out_stage.p, (size_t)m * sizeof(tds_hit),
                                    hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
         }
-        if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
-        // device output is ordered on the batch's stream; host output needs
-        // the copy finished (fetch timing is read by tds_query_stats)
-        if (out_mem == TDS_MEM_HOST) HIP_TRY(hipStreamSynchronize(st));
+        // device output is ordered on the batch's stream (fetch timing is
+        // read by tds_query_stats)
         if (timing) q->fetch_timed = true;
     }
     return TDS_OK;

@@ -164,6 +164,23 @@ def test_overflow_retry():
     with pytest.raises(tds.TdsError) as e:
         run(db, q, 8, capacity=1, max_retries=0)
     assert e.value.code == L.TDS_EOVERFLOW
+    # device output under a re-run: the translation enqueued before the wait
+    # predates the re-run and is redone
+    got, st, _ = run(db, q, 8, mode="fp32_refine", capacity=1, max_retries=2, out="device")
+    compare(got, want, db, "retry device output")
+    assert st["retries"] == 1
+    # the same handle fetched repeatedly: its output buffer is sized from the
+    # previous batch, so the early translation covers every hit (host and
+    # device output)
+    ix = tds.build_index(db, 8)
+    qh = tds.Query(ix)
+    try:
+        for rep, out in enumerate(("host", "device", "host", "device")):
+            qh.batch(q, q.d, mode="fp32_refine", tiling="range")
+            compare(qh.fetch(out=out).sorted(), want, db, f"repeated fetch {rep} {out}")
+    finally:
+        qh.close()
+        ix.close()
     # a dense box under the same small capacity
     db, q = fx.dense_box(ntraj=200, L=30, box=4.0, nq=20, seed=41, d=1.5)
     want = oracle.search(db, q)
