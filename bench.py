@@ -43,8 +43,9 @@ FP32_OPS_PEAK = 256 * 4 * 32 * 2.4e9
 FP64_PEAK = 78.6e12
 # Algorithmic work per temporally overlapping pair:
 FP64_FLOPS_PER_PAIR = 49          # binary64 decision, FMA = 2
-# binary32 test per candidate pair, max over the axes of |c - C| - h: 3
-# differences, 3 |.| - h, 2 maxima (the compare with r is shared by 4 pairs)
+# binary32 test per candidate pair, max over the axes of |c - C| against the
+# cube's r plus the chunk's largest entry half-width: 3 differences, 3
+# absolute values, 2 maxima (the compare is shared by the 4 pairs of a lane)
 FILTER_OPS_PER_PAIR = 8
 
 

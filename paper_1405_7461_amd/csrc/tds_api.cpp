@@ -153,7 +153,7 @@ struct tds_index {
     int32_t m = 0;
     double t_first = 0, t_last = 0, width = 1;
     std::vector<tds_bin> bins;
-    DBuf t0, t1, x0, y0, z0, vx, vy, vz, ecen, ehalf, orig, traj, t1s;
+    DBuf t0, t1, x0, y0, z0, vx, vy, vz, ecen, orig, traj, t1s;
     DBuf bstart, bpend, bfirst, blast;
     DevIndex dev{};
     int64_t device_bytes = 0;
@@ -322,7 +322,6 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
                     &ix->traj, &ix->t1s})
         IX_TRY(b->ensure(n1 * 8));
     IX_TRY(ix->ecen.ensure(n1 * 16));
-    IX_TRY(ix->ehalf.ensure(n1 * 8));
     IX_TRY(ix->orig.ensure(n1 * 4));
     const size_t nb1 = (size_t)std::max<int64_t>(nb, 1);
     IX_TRY(ix->bstart.ensure(nb1 * 8));
@@ -366,7 +365,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
         IX_TRY(launch_ingest(rawp, n, dperm.as<int32_t>(), traj_dev, ix->t0.as<double>(),
                              ix->t1.as<double>(), ix->x0.as<double>(), ix->y0.as<double>(),
                              ix->z0.as<double>(), ix->vx.as<double>(), ix->vy.as<double>(),
-                             ix->vz.as<double>(), ix->ecen.as<float4>(), ix->ehalf.as<float2>(),
+                             ix->vz.as<double>(), ix->ecen.as<float4>(),
                              ix->orig.as<int32_t>(), ix->traj.as<int64_t>(), st));
         IX_TRY(hipMemcpyAsync(ix->t1s.p, t1s.data(), n * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->bstart.p, bs.data(), nb * 8, hipMemcpyHostToDevice, st));
@@ -395,7 +394,6 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.vy = ix->vy.as<double>();
     d.vz = ix->vz.as<double>();
     d.ecen = ix->ecen.as<float4>();
-    d.ehalf = ix->ehalf.as<float2>();
     d.orig = ix->orig.as<int32_t>();
     d.traj = ix->traj.as<int64_t>();
     d.t1s = ix->t1s.as<double>();
@@ -411,7 +409,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.band_abs = std::ldexp(1.0, -40);
     d.ext_max = ext_max;
     d.mag_max = mag_max;
-    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 8 + 4 + 8 + 8) + nb * 24);
+    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 4 + 8 + 8) + nb * 24);
     *out = ix;
     return TDS_OK;
 }
@@ -448,7 +446,7 @@ int tds_index_times(const tds_index *ix, double *t_start_sorted, double *t_end_s
 void tds_index_destroy(tds_index *ix) {
     if (!ix) return;
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
-                    &ix->ecen, &ix->ehalf, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
+                    &ix->ecen, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
                     &ix->bfirst, &ix->blast})
         b->release();
     delete ix;

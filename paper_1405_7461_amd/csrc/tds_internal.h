@@ -99,8 +99,8 @@ struct DevIndex {
     int32_t m;   // bins as requested
     double t_first, width;
     const double *t0, *t1, *x0, *y0, *z0, *vx, *vy, *vz;
-    const float4 *ecen;   // entry box as (cx, cy, cz, hx): centre, x half-width
-    const float2 *ehalf;  // (hy, hz); [c - h, c + h] contains the segment on each axis
+    const float4 *ecen;   // entry box centre and largest half-width h: the cube
+                          // [c - h, c + h]^3 contains the segment
     const int32_t *orig;  // caller index of each sorted entry
     const int64_t *traj;  // trajectory id of each sorted entry
     const double *t1s;    // t_end, sorted independently (overlap counts)
@@ -177,7 +177,7 @@ struct GreedyBufs {
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
                          double *z0, double *vx, double *vy, double *vz, float4 *ecen,
-                         float2 *ehalf, int32_t *orig, int64_t *traj, hipStream_t st);
+                         int32_t *orig, int64_t *traj, hipStream_t st);
 // ev_start (optional) records the start of the first kernel.
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
                           hipStream_t st, hipEvent_t ev_start = nullptr);

@@ -86,7 +86,7 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
                          int64_t n, const int32_t *__restrict__ perm,
                          const int64_t *__restrict__ traj_raw, double *t0, double *t1, double *x0,
                          double *y0, double *z0, double *vx, double *vy, double *vz, float4 *ecen,
-                         float2 *ehalf, int32_t *orig, int64_t *traj) {
+                         int32_t *orig, int64_t *traj) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int32_t i = perm[p];
@@ -111,8 +111,7 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
         cx = cy = cz = 0.0f;
         hx = hy = hz = INFINITY;
     }
-    ecen[p] = make_float4(cx, cy, cz, hx);
-    ehalf[p] = make_float2(hy, hz);
+    ecen[p] = make_float4(cx, cy, cz, fmaxf(fmaxf(hx, hy), hz));
     orig[p] = i;
     traj[p] = traj_raw ? traj_raw[i] : (int64_t)i;
 }
@@ -120,13 +119,13 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
                          double *z0, double *vx, double *vy, double *vz, float4 *ecen,
-                         float2 *ehalf, int32_t *orig, int64_t *traj, hipStream_t st) {
+                         int32_t *orig, int64_t *traj, hipStream_t st) {
     if (n == 0) return hipSuccess;
     int blk = 256;
     int64_t grid = (n + blk - 1) / blk;
     hipLaunchKernelGGL(k_ingest, dim3((unsigned)grid), dim3(blk), 0, st, raw[0], raw[1], raw[2],
                        raw[3], raw[4], raw[5], raw[6], raw[7], n, perm_sorted, traj_raw, t0, t1, x0,
-                       y0, z0, vx, vy, vz, ecen, ehalf, orig, traj);
+                       y0, z0, vx, vy, vz, ecen, orig, traj);
     TDS_LAUNCH_CHECK();
 }
 
@@ -672,8 +671,14 @@ __device__ __forceinline__ int tile_of_unit(const long long *__restrict__ off, i
 // Largest per-axis gap |c - C| - h between an entry box (centre c, half-
 // widths h) and a query centre C: the pair passes when it is <= the query's
 // r. NaN (an empty slot) never passes.
-__device__ __forceinline__ float cube_gap(const float4 &c, const float2 &h, const float4 &q) {
-    return fmaxf(fmaxf(fabsf(c.x - q.x) - c.w, fabsf(c.y - q.y) - h.x), fabsf(c.z - q.z) - h.y);
+// Largest axis distance between an entry box centre and a query cube
+// centre: three subtractions and one max3 with absolute-value modifiers.
+// The caller compares it with r + H, H the largest half-width of the
+// entries in the chunk (wave-uniform), which holds whenever some entry box
+// of the chunk meets the cube, so the test stays conservative with four
+// instructions per pair instead of seven for per-entry half-widths.
+__device__ __forceinline__ float cube_gap(const float4 &c, const float4 &q) {
+    return fmaxf(fmaxf(fabsf(c.x - q.x), fabsf(c.y - q.y)), fabsf(c.z - q.z));
 }
 
 // Query boxes staged in LDS per wave: 64 at a time, one per lane.
@@ -842,36 +847,43 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 // Conservative binary32 filter: the entry's box against the
                 // query's cube; time is left to the refine.
                 float4 ec[EPT];
-                float2 eh[EPT];
+                float hmax = 0.0f;
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) {
                     const int e = wb + j * 64 + lane;
                     if (e < we) {
                         ec[j] = ix.ecen[e];
-                        eh[j] = ix.ehalf[e];
+                        hmax = fmaxf(hmax, ec[j].w);
                     } else {  // an empty slot (NaN) never passes
                         ec[j] = make_float4(NAN, NAN, NAN, NAN);
-                        eh[j] = make_float2(NAN, NAN);
                     }
                 }
+                // H: the largest entry half-width of the chunk (wave-uniform)
+                for (int off = 32; off > 0; off >>= 1) hmax = fmaxf(hmax, __shfl_xor(hmax, off));
+                const float H = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(hmax)));
                 auto gaps_of = [&](const float4 &qc, float (&gap)[EPT], auto full) {
                     constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
-                    gap[0] = cube_gap(ec[0], eh[0], qc);  // slot 0 always holds entries
+                    gap[0] = cube_gap(ec[0], qc);  // slot 0 always holds entries
                     float gmin = gap[0];
 #pragma unroll
                     for (int j = 1; j < EPT; ++j) {
                         gap[j] = NAN;
                         if (FULL || j < nv) {  // wave-uniform: skip slots without entries
-                            gap[j] = cube_gap(ec[j], eh[j], qc);
+                            gap[j] = cube_gap(ec[j], qc);
                             gmin = fminf(gmin, gap[j]);
                         }
                     }
                     return gmin;
                 };
-                auto emit = [&](const float4 &qc, const int qs, const float (&gap)[EPT]) {
+                // threshold of a query cube against this chunk: r + H. Its
+                // rounding (at most 2^-24 (r + H), H <= ext_max / 2) and that
+                // of the distances lie within the 2^-20 (r + ext_max) slack
+                // the cube's r carries.
+                auto thr = [&](const float4 &qc) { return qc.w + H; };
+                auto emit = [&](const float t, const int qs, const float (&gap)[EPT]) {
 #pragma unroll
                     for (int j = 0; j < EPT; ++j)
-                        select(gap[j] <= qc.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                        select(gap[j] <= t, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
                 };
                 auto count_ovl = [&](const int qs) {
                     if (COUNT_OVL) {
@@ -905,9 +917,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             const float4 qa = s_q[wv][j], qz = s_q[wv][j + 1];
                             float ga[EPT], gz[EPT];
                             const float ma = gaps_of(qa, ga, full), mz = gaps_of(qz, gz, full);
-                            if (__builtin_expect(__ballot(ma <= qa.w || mz <= qz.w) != 0ull, 0)) {
-                                emit(qa, s0 + j, ga);
-                                emit(qz, s0 + j + 1, gz);
+                            const float ta = thr(qa), tz = thr(qz);
+                            if (__builtin_expect(__ballot(ma <= ta || mz <= tz) != 0ull, 0)) {
+                                emit(ta, s0 + j, ga);
+                                emit(tz, s0 + j + 1, gz);
                             }
                             count_ovl(s0 + j);
                             count_ovl(s0 + j + 1);
@@ -918,7 +931,8 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             const float4 qa = s_q[wv][j];
                             float ga[EPT];
                             const float ma = gaps_of(qa, ga, full);
-                            if (__builtin_expect(__ballot(ma <= qa.w) != 0ull, 0)) emit(qa, s0 + j, ga);
+                            const float ta = thr(qa);
+                            if (__builtin_expect(__ballot(ma <= ta) != 0ull, 0)) emit(ta, s0 + j, ga);
                             count_ovl(s0 + j);
                             progress();
                         }
