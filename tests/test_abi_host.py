@@ -157,3 +157,10 @@ def test_query_tiles_arguments():
     a, b = C.c_int64(), C.c_int64()
     assert lib.tds_query_tiles(None, None, 0, None, 0, C.byref(a), C.byref(b)) == L.TDS_EINVAL
     assert b"tds_query_tiles" in lib.tds_last_error()
+
+
+def test_index_times_arguments():
+    import ctypes as C
+    lib = L.lib()
+    assert lib.tds_index_times(None, None, None, 0) == L.TDS_EINVAL
+    assert b"tds_index_times" in lib.tds_last_error()

@@ -294,3 +294,45 @@ def test_torch_allocator_hook():
     # buffers made afterwards come from HIP again
     got, st, _ = run(db, q, m)
     compare(got, want, db, "hip allocator again")
+
+
+def test_extreme_magnitudes():
+    # Chunks that mix ordinary entries with entries beyond 2^100 (whose boxes
+    # are unbounded, so the chunk's largest half-width is infinite and every
+    # pair goes to the refine) and with very long segments; query segments
+    # copy some of the huge entries (distance 0: hits among huge values) and
+    # sit among the ordinary ones. A second case at the scale 1e-6 with a
+    # threshold of 1e-7.
+    rng = np.random.default_rng(17)
+
+    def rows_for(n, scale, huge_every, long_every, seed_shift=0.0):
+        out = []
+        for i in range(n):
+            p0 = rng.uniform(-5, 5, 3) * scale
+            p1 = p0 + rng.normal(0, 0.5, 3) * scale
+            if huge_every and i % huge_every == 7:
+                p0, p1 = p0 * 1e31 / scale, p1 * 1e31 / scale
+            if long_every and i % long_every == 13:
+                p1 = p0 + rng.normal(0, 200, 3) * scale
+            t0 = rng.uniform(0, 5)
+            out.append([*p0, t0 + seed_shift, *p1, t0 + seed_shift + rng.uniform(0.5, 2)])
+        return np.array(out)
+
+    e = rows_for(600, 1.0, 50, 50)
+    qrows = rows_for(40, 1.0, 0, 0)
+    qrows = np.vstack([qrows, e[7::100]])  # copies of huge entries
+    db = fx.segments_from_rows(e)
+    q = fx.segments_from_rows(qrows).with_d(1.0)
+    want = oracle.search(db, q)
+    assert len(want) > 5
+    for mode in MODES:
+        got, _, _ = run(db, q, 8, mode=mode)
+        compare(got, want, db, f"huge and long {mode}")
+    e = rows_for(600, 1e-6, 0, 0)
+    db = fx.segments_from_rows(e)
+    q = fx.segments_from_rows(e[::15] + np.array([1e-8, 0, 0, 0, 1e-8, 0, 0, 0])).with_d(1e-7)
+    want = oracle.search(db, q)
+    assert len(want) >= 40
+    for mode in MODES:
+        got, _, _ = run(db, q, 8, mode=mode)
+        compare(got, want, db, f"scale 1e-6 {mode}")
