@@ -244,9 +244,10 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         double w = d + ix.band_rel * (d + ext + ix.ext_max) +
                    ix.band_abs * (1.0 + d + mag + ext + ix.mag_max + ix.ext_max);
         // The widened box as a cube: centre C and the largest half-width r.
-        // The binary32 test computes |c - C| - h per axis; its rounding stays
-        // below 2^-22 (r + h + |c - C|) for pairs near the threshold, covered
-        // by the 2^-20 (r + ext_max) slack (entry half-widths are at most
+        // The binary32 test compares max_axis |c - C| with r + H (H the
+        // largest entry half-width of a chunk); its rounding stays below
+        // 2^-22 (r + H) for pairs near the threshold, covered by the
+        // 2^-20 (r + ext_max) slack (entry half-widths are at most
         // ext_max / 2).
         QCube32 bx;
         if (mag + w <= kCubeLimit) {
