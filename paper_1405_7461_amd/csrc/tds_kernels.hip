@@ -48,11 +48,7 @@ namespace tds {
 __device__ __forceinline__ double dmx(double a, double b) { return __builtin_fmax(a, b); }
 __device__ __forceinline__ double dmn(double a, double b) { return __builtin_fmin(a, b); }
 
-// binary32 neighbours of a binary64 value: largest float <= x, smallest >= x.
-__device__ __forceinline__ float f32_down(double x) {
-    float f = (float)x;
-    return ((double)f > x) ? nextafterf(f, -INFINITY) : f;
-}
+// Smallest binary32 value >= a binary64 value.
 __device__ __forceinline__ float f32_up(double x) {
     float f = (float)x;
     return ((double)f < x) ? nextafterf(f, INFINITY) : f;
