@@ -165,7 +165,7 @@ struct tds_query {
     int32_t cap_q = 0;        // query slots allocated
     int32_t cap_buckets = 0;  // bucket slots allocated
     DBuf rec, box, first, last, first_s, last_s, key, perm;
-    DBuf qrank, bcount, bj2, bq_off, tiles, units, unit_off, ctr;
+    DBuf qrank, bcount, bj2, bq_off, tiles, units, unit_off, cost_off, ctr;
     DBuf qstage, cand, hits, slab_n, slab_h, hit_off, wave_ovl, out_stage;
     DBuf tr_qtraj, tr_work, tr_temp, tr_out;  // trajectory merge
     DBuf gs_work, gs_jump;                     // GreedySetSplit tiling
@@ -479,7 +479,7 @@ void tds_query_destroy(tds_query *q) {
     if (q->pending) (void)hipStreamSynchronize(q->stream);
     for (DBuf *b : {&q->rec, &q->box, &q->first, &q->last, &q->first_s,
                     &q->last_s, &q->key, &q->perm, &q->qrank, &q->bcount, &q->bj2, &q->bq_off,
-                    &q->tiles, &q->units, &q->unit_off, &q->ctr, &q->qstage, &q->cand,
+                    &q->tiles, &q->units, &q->unit_off, &q->cost_off, &q->ctr, &q->qstage, &q->cand,
                     &q->hits, &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage,
                     &q->tr_qtraj, &q->tr_work, &q->tr_temp, &q->tr_out, &q->gs_work,
                     &q->gs_jump})
@@ -504,6 +504,7 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
         HIP_TRY(q->tiles.ensure(n1 * sizeof(Tile)));
         HIP_TRY(q->units.ensure(n1 * 8));
         HIP_TRY(q->unit_off.ensure(n1 * 8));
+        HIP_TRY(q->cost_off.ensure(n1 * 8));
         HIP_TRY(q->ctr.ensure(sizeof(Counters)));
         q->cap_q = c;
     }
@@ -682,6 +683,8 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.nbuckets = nbuckets;
     b.ntiles_cap = o.tiling == TDS_TILE_PERIODIC ? (nq + o.batch_size - 1) / o.batch_size : nq;
     b.count_overlap = (o.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0;
+    b.pass_cost = o.mode == TDS_MODE_FP64 ? TDS_PASS_COST64 : TDS_PASS_COST32;
+    b.stage_cost = o.mode == TDS_MODE_FP64 ? TDS_STAGE_COST64 : TDS_STAGE_COST32;
     b.rec = q->rec.as<QRec64>();
     b.box = q->box.as<QCube32>();
     b.first = q->first.as<int32_t>();
@@ -697,6 +700,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.tiles = q->tiles.as<Tile>();
     b.units = q->units.as<long long>();
     b.unit_off = q->unit_off.as<long long>();
+    b.cost_off = q->cost_off.as<long long>();
     b.ctr = q->ctr.as<Counters>();
 
     const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;

@@ -318,26 +318,31 @@ __global__ void k_gs_tiles(DevBatch b, GreedyBufs g) {
     }
 }
 
-// One block: unit offsets of the tiles, the tile count, the work units and
-// the interactions (n_eval).
+// One block: unit and cost offsets of the tiles, the tile count, the work
+// units and the interactions (n_eval).
 __global__ __launch_bounds__(kChainBlock) void k_gs_unit_scan(DevBatch b, GreedyBufs g) {
     const int n = g.cnt[1];
     const int per = (n + kChainBlock - 1) / kChainBlock;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
-    long long s = 0, ev = 0;
+    long long s = 0, ev = 0, k_sum = 0;
     for (int k = lo; k < hi; ++k) {
         s += b.units[k];
         ev += g.tev[k];
+        k_sum += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
     }
-    long long tot, ev_tot;
+    long long tot, ev_tot, k_tot;
     long long run = gs_block_scan(s, &tot);
     (void)gs_block_scan(ev, &ev_tot);
+    long long k_run = gs_block_scan(k_sum, &k_tot);
     for (int k = lo; k < hi; ++k) {
         b.unit_off[k] = run;
+        b.cost_off[k] = k_run;
         run += b.units[k];
+        k_run += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
     }
     if (threadIdx.x == 0) {
         b.unit_off[n] = tot;
+        b.cost_off[n] = k_tot;
         b.ctr->n_tiles = (unsigned)n;
         b.ctr->n_units = (unsigned long long)tot;
         b.ctr->n_eval = (unsigned long long)ev_tot;

@@ -44,6 +44,35 @@ __host__ __device__ inline int chunk_entries(int ne, int nchunk) {
     return (per + 63) & ~63;
 }
 
+// The pair kernel splits a batch over its waves by cost rather than by work
+// units (query segment x entry chunk): a pass over one chunk of a tile costs
+// its nq segments plus a fixed overhead (loading the chunk and staging the
+// first segments) and a further one per extra stage of 64 segments. Tiles of
+// few segments are then no longer cheap for the waves that draw many of them.
+#ifndef TDS_PASS_COST32
+#define TDS_PASS_COST32 24
+#endif
+#ifndef TDS_STAGE_COST32
+#define TDS_STAGE_COST32 4
+#endif
+#ifndef TDS_PASS_COST64
+#define TDS_PASS_COST64 2
+#endif
+#ifndef TDS_STAGE_COST64
+#define TDS_STAGE_COST64 0
+#endif
+
+// Overhead of one pass of a tile with nq segments, in work units.
+__host__ __device__ inline long long pass_overhead(int nq, int pass_cost, int stage_cost) {
+    return (long long)pass_cost + (long long)stage_cost * ((nq + 63) / 64 - 1);
+}
+
+// Cost of a whole tile: nchunk passes (0 for a tile without work).
+__host__ __device__ inline long long tile_cost(int nq, int nchunk, int pass_cost, int stage_cost) {
+    if (nq <= 0 || nchunk <= 0) return 0;
+    return (long long)nchunk * ((long long)nq + pass_overhead(nq, pass_cost, stage_cost));
+}
+
 // A pair selected by the pair kernel (sorted query / sorted entry positions).
 struct Cand {
     uint32_t q, e;
@@ -129,6 +158,8 @@ struct DevBatch {
     int32_t nbuckets;
     int32_t ntiles_cap;
     int32_t count_overlap;      // exact overlap count in the query preparation
+    int32_t pass_cost;          // pair-kernel cost of a chunk pass beyond its segments
+    int32_t stage_cost;         // ... and of each further stage of 64 segments
     int32_t pad;
     QRec64 *rec;          // caller order
     QCube32 *box;         // caller order
@@ -142,6 +173,7 @@ struct DevBatch {
     Tile *tiles;
     long long *units;           // per tile (periodic)
     long long *unit_off;        // exclusive scan of units per tile (+ total)
+    long long *cost_off;        // exclusive scan of tile costs (+ total)
     Counters *ctr;
 };
 

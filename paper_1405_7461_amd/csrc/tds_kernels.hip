@@ -419,15 +419,17 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
             if (range && *c > 0) bucket_range(b, ix, lo + r, e0, ne);
         }
     };
-    long long c_sum = 0, t_sum = 0, u_sum = 0;
+    long long c_sum = 0, t_sum = 0, u_sum = 0, k_sum = 0;
     unsigned long long ev = 0;
     auto tally = [&](int r) {
         int c, e0, ne;
         get(r, &c, &e0, &ne);
         c_sum += c;
         if (range && c > 0) {
+            const int nch = (ne + b.chunk - 1) / b.chunk;
             t_sum += 1;
-            u_sum += (long long)((ne + b.chunk - 1) / b.chunk) * c;
+            u_sum += (long long)nch * c;
+            k_sum += tile_cost(c, nch, b.pass_cost, b.stage_cost);
             ev += (unsigned long long)c * (unsigned long long)ne;
         }
     };
@@ -438,10 +440,11 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
     } else {
         for (int r = 0; r < hi - lo; ++r) tally(r);
     }
-    long long c_tot, t_tot, u_tot;
+    long long c_tot, t_tot, u_tot, k_tot;
     long long c_run = block_exclusive_scan<kScanBlock>(c_sum, &c_tot);
     long long t_run = block_exclusive_scan<kScanBlock>(t_sum, &t_tot);
     long long u_run = block_exclusive_scan<kScanBlock>(u_sum, &u_tot);
+    long long k_run = block_exclusive_scan<kScanBlock>(k_sum, &k_tot);
     auto place = [&](int r) {
         const int k = lo + r;
         int c, e0, ne;
@@ -463,8 +466,10 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
             tl.pad0 = tl.pad1 = 0;
             b.tiles[t_run] = tl;
             b.unit_off[t_run] = u_run;
+            b.cost_off[t_run] = k_run;
             t_run += 1;
             u_run += (long long)tl.nchunk * c;
+            k_run += tile_cost(c, tl.nchunk, b.pass_cost, b.stage_cost);
         }
         c_run += c;
     };
@@ -483,6 +488,7 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
             b.ctr->n_tiles = (unsigned)t_tot;
             b.ctr->n_units = (unsigned long long)u_tot;
             b.unit_off[t_tot] = u_tot;
+            b.cost_off[t_tot] = k_tot;
         }
     }
 }
@@ -536,23 +542,30 @@ __global__ void k_periodic_tiles(DevBatch b) {
     }
 }
 
-// One block: exclusive scan of the periodic tiles' work units.
+// One block: exclusive scans of the periodic tiles' work units and costs.
 __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
     const int n = b.ntiles_cap;
     const int per = (n + kScanBlock - 1) / kScanBlock;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
-    long long s = 0;
-    for (int k = lo; k < hi; ++k) s += b.units[k];
-    long long tot;
+    long long s = 0, k_sum = 0;
+    for (int k = lo; k < hi; ++k) {
+        s += b.units[k];
+        k_sum += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
+    }
+    long long tot, k_tot;
     long long run = block_exclusive_scan<kScanBlock>(s, &tot);
+    long long k_run = block_exclusive_scan<kScanBlock>(k_sum, &k_tot);
     for (int k = lo; k < hi; ++k) {
         b.unit_off[k] = run;
+        b.cost_off[k] = k_run;
         run += b.units[k];
+        k_run += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
     }
     if (threadIdx.x == 0) {
         b.ctr->n_tiles = (unsigned)n;
         b.ctr->n_units = (unsigned long long)tot;
         b.unit_off[n] = tot;
+        b.cost_off[n] = k_tot;
     }
 }
 
@@ -646,7 +659,8 @@ __device__ __forceinline__ void interval64(const Pair64 &p, double *ta, double *
 }
 
 // Tile owning work unit u: the last t in [0, n) with off[t] <= u (tiles
-// without units share their successor's offset; off[0] = 0 <= u). A 64-way
+// without units share their successor's offset; off[0] = 0 <= u). The same
+// search finds the tile owning a cost position in the cost offsets. A 64-way
 // search: each round the lanes probe 64 evenly spaced offsets of [lo, hi) and
 // the last probe <= u becomes lo, so n tiles take ceil(log64 n) rounds.
 __device__ __forceinline__ int tile_of_unit(const long long *__restrict__ off, int n, long long u) {
@@ -723,7 +737,9 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                                                 const QCube32 *__restrict__ box,
                                                 const int32_t *__restrict__ perm, int nq,
                                                 const Tile *__restrict__ tiles,
-                                                const long long *__restrict__ unit_off, DevIndex ix,
+                                                const long long *__restrict__ unit_off,
+                                                const long long *__restrict__ cost_off,
+                                                int pass_cost, int stage_cost, DevIndex ix,
                                                 Slabs sl, Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
     const long long nwaves = (long long)gridDim.x * (BLOCK / 64);
@@ -944,13 +960,26 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
         ++t;
     }
     };
-    // Even static split over the launched waves (every wave is resident from
-    // the start, see resident_blocks). The SIMD issues the oldest ready wave
-    // first, so without correction the first waves finish early and the last
-    // ones run nearly alone; each wave therefore lowers its priority by one
-    // step per quarter of its share done, keeping the waves of a SIMD at
+    // Even static split of the batch's cost over the launched waves (every
+    // wave is resident from the start, see resident_blocks). A cost position
+    // maps to the first work unit at or after it; the overhead of a chunk
+    // pass counts before its first segment. The SIMD issues the oldest ready
+    // wave first, so without correction the first waves finish early and the
+    // last ones run nearly alone; each wave therefore lowers its priority by
+    // one step per quarter of its share done, keeping the waves of a SIMD at
     // similar progress so they finish together.
-    const long long u0 = (w * total) / nwaves, u1 = ((w + 1) * total) / nwaves;
+    const long long ctot = rfl64(cost_off[ntiles]);
+    auto unit_at = [&](const long long c) -> long long {
+        if (c >= ctot) return total;
+        const int t = tile_of_unit(cost_off, ntiles, c);
+        const Tile tl = tiles[t];
+        const long long ov = pass_overhead(tl.nq, pass_cost, stage_cost);
+        const long long lc = c - cost_off[t];
+        const long long ch = lc / (tl.nq + ov);
+        const long long r = lc - ch * (tl.nq + ov) - ov;
+        return unit_off[t] + ch * tl.nq + (r > 0 ? r : 0);
+    };
+    const long long u0 = unit_at((w * ctot) / nwaves), u1 = unit_at(((w + 1) * ctot) / nwaves);
     pr_step = (int)max(1LL, min((u1 - u0) / 4, (long long)INT_MAX));
     pr_next = pr_step;
     set_prio(3);
@@ -1125,10 +1154,12 @@ static hipError_t launch_pair_b(DevBatch b, DevIndex ix, int grid, int kernel_ov
         return hipErrorInvalidValue;  // slabs sized for another launch
     if (kernel_overlap)
         TDS_LAUNCH_EV(ev0, ev1, (k_pair<MODE, BLOCK, EPT, true>), dim3(g), dim3(BLOCK), 0, st,
-                      b.rec, b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
+                      b.rec, b.box, b.perm, b.nq, b.tiles, b.unit_off, b.cost_off,
+                      b.pass_cost, b.stage_cost, ix, sl, b.ctr);
     else
         TDS_LAUNCH_EV(ev0, ev1, (k_pair<MODE, BLOCK, EPT, false>), dim3(g), dim3(BLOCK), 0, st,
-                      b.rec, b.box, b.perm, b.nq, b.tiles, b.unit_off, ix, sl, b.ctr);
+                      b.rec, b.box, b.perm, b.nq, b.tiles, b.unit_off, b.cost_off,
+                      b.pass_cost, b.stage_cost, ix, sl, b.ctr);
     TDS_LAUNCH_CHECK();
 }
 
