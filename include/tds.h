@@ -86,7 +86,9 @@ typedef struct {
 #define TDS_MODE_FP32_REFINE 1  /* binary32 conservative filter, binary64 decision of survivors */
 
 /* How query segments are grouped into tiles (batches, Sec. 6). */
-#define TDS_TILE_PERIODIC 0     /* consecutive runs of batch_size segments in t_start order ("Periodic") */
+/* Periodic (Sec. 6): consecutive runs of batch_size query segments with
+ * candidates, in (t_start, caller index) order. */
+#define TDS_TILE_PERIODIC 0
 #define TDS_TILE_RANGE 1        /* runs of <= batch_size segments with the same candidate bin range */
 /* GreedySetSplit (Sec. 6, Alg. 4) over the query segments with candidates in
  * (t_start, caller index) order: first every run of consecutive segments with

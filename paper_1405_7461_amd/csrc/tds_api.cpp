@@ -521,16 +521,17 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
 // chain is marked with `levels` doubling passes, enough for 2^levels - 1
 // batches: with Min every batch but the last holds at least `bound`
 // segments, with Max two neighbouring batches hold more than `bound`.
-static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, GreedyBufs *g) {
+static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, bool chain,
+                          GreedyBufs *g) {
     const long long most = is_max ? 2LL * nq / ((long long)bound + 1) + 2 : (long long)nq / bound + 2;
     int levels = 1;
-    while ((1LL << levels) <= most) ++levels;
+    while (chain && (1LL << levels) <= most) ++levels;
     const size_t n = (size_t)nq, n1 = n + 1;
     // 8-byte arrays first: kin, tev; then the 4-byte ones, then the flags
     const size_t n16 = (n + 15) & ~(size_t)15;
     const size_t bytes = n * 8 * 2 + n * 4 + n1 * 4 * 3 + 2 * 4 + n16 + 64;
     HIP_TRY(q->gs_work.ensure(bytes));
-    HIP_TRY(q->gs_jump.ensure((size_t)levels * n1 * 4));
+    if (chain) HIP_TRY(q->gs_jump.ensure((size_t)levels * n1 * 4));
     char *w = q->gs_work.as<char>();
     auto take = [&](size_t b) { char *p = w; w += b; return p; };
     g->kin = (unsigned long long *)take(n * 8);
@@ -703,15 +704,24 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.cost_off = q->cost_off.as<long long>();
     b.ctr = q->ctr.as<Counters>();
 
+    // Periodic and the greedy tilings walk the segments in exact
+    // (t_start, caller index) order, sorted within each t_start bin
     const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
+    const bool sorted = greedy || o.tiling == TDS_TILE_PERIODIC;
     GreedyBufs gb{};
-    if (greedy && nq > 0) {
-        rc = greedy_buffers(q, nq, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, &gb);
+    b.skey = nullptr;
+    b.sidx = nullptr;
+    if (sorted && nq > 0) {
+        rc = greedy_buffers(q, nq, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, greedy, &gb);
         if (rc) return rc;
+        b.skey = gb.kin;
+        b.sidx = gb.vout;
     }
 
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
     HIP_TRY(launch_prepare(qin, din, b, ix->dev, st, timing ? q->ev[0] : nullptr));
+    if (sorted && nq > 0) HIP_TRY(launch_bucket_sort(b, st));
+    if (o.tiling == TDS_TILE_PERIODIC && nq > 0) HIP_TRY(launch_periodic(b, st));
     if (greedy && nq > 0)
         HIP_TRY(launch_greedy(b, gb, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, st));
     rc = launch_search(q);

@@ -19,9 +19,8 @@
 // jump_k images. L levels cover chains of fewer than 2^L batches.
 //
 // Launches: the exact (t_start, caller index) order within each t_start bin
-// (the query preparation's counting sort already orders the bins), with a
-// fallback for bins too large for LDS; placement of the sorted order with
-// the run flags; one workgroup for groups, chain and batch starts (in LDS
+// (the query preparation's counting sort already orders the bins; this
+// launch also orders Periodic tiling); the run flags; one workgroup for groups, chain and batch starts (in LDS
 // when there are fewer than kChainLds groups); the tiles; one workgroup for
 // the unit offsets.
 #include <hip/hip_runtime.h>
@@ -32,112 +31,181 @@ namespace tds {
 
 namespace {
 
-__device__ __forceinline__ unsigned long long start_bits(double x) {
-    x = x + 0.0;  // -0 sorts with +0
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-
 // Exact (t_start, caller index) order within each t_start bin (the bins
 // are already in order: the counting sort of the query preparation put the
-// segments of bin k at bq_off[k] .. bq_off[k] + bcount[k] - 1 of perm, in
-// no particular order). One workgroup per bin: up to kSortLds segments are
-// sorted in LDS by a bitonic network on (order bits of t_start, caller
-// index), a unique key; larger bins only get their keys written in bin order
-// for k_gs_rank_big.
+// segments of bin k at positions bq_off[k] .. bq_off[k] + bcount[k] - 1, in
+// no particular order, with their keys in skey / sidx). The key (order bits
+// of t_start, caller index) is unique, so a segment's place is its bin
+// offset plus the number of bin members with a smaller key. Blocks below
+// nbuckets take one bin of at most kSortLds segments each and rank it in
+// LDS: by counting (broadcast reads) up to kCountMax segments, by a bitonic
+// network above (counting is quadratic: at 512 segments it took 65 us on a
+// batch where the network takes 23 us). The blocks after them rank the members of larger bins by
+// counting over global memory, a grid-stride loop over positions (these bins
+// are rare; k_bucket_scan counts them, and with none the blocks return at
+// once). Reads go to skey / sidx only and writes to perm, first_s, last_s
+// only, so no block sees another's writes.
 constexpr int kSortBlock = 256;
-constexpr int kSortLds = 4096;
+#ifndef TDS_COUNT_MAX
+#define TDS_COUNT_MAX 64
+#endif
+constexpr int kCountMax = TDS_COUNT_MAX;
 
-__global__ __launch_bounds__(kSortBlock) void k_gs_bin_sort(DevBatch b, GreedyBufs g) {
-    __shared__ unsigned long long s_key[kSortLds];
-    __shared__ int32_t s_idx[kSortLds];
-    const int k = blockIdx.x;
-    if (k >= b.nbuckets) return;
-    const int cnt = b.bcount[k];
-    if (cnt <= 0) return;
-    const int off = b.bq_off[k];
+// Bitonic network over P = E * kSortBlock keys (padding sorts last) held in
+// registers: element p = k * kSortBlock + thread is slot k of that thread.
+// A compare-exchange at distance d pairs slots of one thread (d >=
+// kSortBlock), lanes of one wave through shuffles (d < 64), or lanes of
+// different waves through LDS (64 <= d < kSortBlock), so only the LDS steps
+// need the workgroup barrier.
+__device__ __forceinline__ bool key_gt(unsigned long long ka, int ia, unsigned long long kb, int ib) {
+    return ka > kb || (ka == kb && ia > ib);
+}
+
+template <int E, class Put>
+__device__ void bitonic_block(const DevBatch &b, int off, int cnt, unsigned long long *s_key,
+                              int32_t *s_idx, Put put) {
     const int tid = threadIdx.x;
-    if (cnt > kSortLds) {
-        for (int p = tid; p < cnt; p += kSortBlock) g.kin[off + p] = start_bits(b.rec[b.perm[off + p]].t0);
-        return;
+    constexpr int P = E * kSortBlock;
+    unsigned long long key[E];
+    int idx[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int p = k * kSortBlock + tid;
+        key[k] = p < cnt ? b.skey[off + p] : ~0ull;
+        idx[k] = p < cnt ? b.sidx[off + p] : 0x7fffffff;
     }
-    int P = 1;
-    while (P < cnt) P <<= 1;
-    for (int p = tid; p < P; p += kSortBlock) {
-        if (p < cnt) {
-            const int i = b.perm[off + p];
-            s_key[p] = start_bits(b.rec[i].t0);
-            s_idx[p] = i;
-        } else {  // padding sorts last
-            s_key[p] = ~0ull;
-            s_idx[p] = 0x7fffffff;
-        }
-    }
-    __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int p = tid; p < P; p += kSortBlock) {
-                const int l = p ^ stride;
-                if (l > p) {
-                    const unsigned long long ka = s_key[p], kb = s_key[l];
-                    const int ia = s_idx[p], ib = s_idx[l];
-                    const bool a_gt = ka > kb || (ka == kb && ia > ib);
-                    const bool up = (p & size) == 0;
-                    if (a_gt == up) {  // out of order for this direction
-                        s_key[p] = kb;
-                        s_key[l] = ka;
-                        s_idx[p] = ib;
-                        s_idx[l] = ia;
+        for (int d = size >> 1; d > 0; d >>= 1) {
+            if (d >= kSortBlock) {
+                const int ks = d / kSortBlock;
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if (k & ks) continue;
+                    const int k2 = k | ks;
+                    const bool up = ((k * kSortBlock + tid) & size) == 0;
+                    if (key_gt(key[k], idx[k], key[k2], idx[k2]) == up) {
+                        const unsigned long long tk = key[k];
+                        const int ti = idx[k];
+                        key[k] = key[k2];
+                        idx[k] = idx[k2];
+                        key[k2] = tk;
+                        idx[k2] = ti;
                     }
                 }
+                continue;
             }
-            __syncthreads();
+            const bool lower = (tid & d) == 0;  // this element precedes its partner
+            if (d >= 64) {
+                __syncthreads();  // the previous LDS step has been read
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    s_key[k * kSortBlock + tid] = key[k];
+                    s_idx[k * kSortBlock + tid] = idx[k];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                unsigned long long pk;
+                int pi;
+                if (d >= 64) {
+                    pk = s_key[(k * kSortBlock + tid) ^ d];
+                    pi = s_idx[(k * kSortBlock + tid) ^ d];
+                } else {
+                    const unsigned lo = __shfl_xor((unsigned)key[k], d);
+                    const unsigned hi = __shfl_xor((unsigned)(key[k] >> 32), d);
+                    pk = ((unsigned long long)hi << 32) | lo;
+                    pi = __shfl_xor(idx[k], d);
+                }
+                const bool up = ((k * kSortBlock + tid) & size) == 0;
+                // the lower element keeps the smaller key when ascending
+                const bool gt = key_gt(key[k], idx[k], pk, pi);
+                if (lower == up ? gt : !gt) {
+                    key[k] = pk;
+                    idx[k] = pi;
+                }
+            }
         }
     }
-    for (int p = tid; p < cnt; p += kSortBlock) g.vout[off + p] = s_idx[p];
-}
-
-// Bins of more than kSortLds segments: each segment's position in its bin is
-// the number of bin members with a smaller (t_start, caller index) key,
-// counted over the keys k_gs_bin_sort wrote (quadratic in the bin size, but
-// only for bins too large for LDS).
-__global__ void k_gs_rank_big(DevBatch b, GreedyBufs g) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int)b.ctr->n_sorted) return;
-    const int i = b.perm[p];
-    const int k = b.key[i];
-    const int cnt = b.bcount[k];
-    if (cnt <= kSortLds) return;
-    const int off = b.bq_off[k];
-    const unsigned long long mine = g.kin[p];
-    int rank = 0;
-    for (int q = off; q < off + cnt; ++q) {
-        const unsigned long long o = g.kin[q];
-        rank += (o < mine || (o == mine && b.perm[q] < i)) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int p = k * kSortBlock + tid;
+        if (p < cnt) put(off + p, idx[k]);
     }
-    g.vout[off + rank] = i;
 }
 
-// Sorted order -> perm, sorted ranges, run-start flags (one byte per
-// position; positions past the segments with candidates, up to the next
-// multiple of 16, get 0).
-__global__ void k_gs_place(DevBatch b, GreedyBufs g, int n16) {
+__global__ __launch_bounds__(kSortBlock) void k_gs_bin_sort(DevBatch b) {
+    __shared__ unsigned long long s_key[kSortLds];
+    __shared__ int32_t s_idx[kSortLds];
+    const int tid = threadIdx.x;
+    auto put = [&](int p, int i) {
+        b.perm[p] = i;
+        b.first_s[p] = b.first[i];
+        b.last_s[p] = b.last[i];
+    };
+    if ((int)blockIdx.x >= b.nbuckets) {  // members of bins too large for LDS
+        if (b.ctr->big_bins == 0) return;
+        const int ns = (int)b.ctr->n_sorted;
+        const int stride = ((int)gridDim.x - b.nbuckets) * kSortBlock;
+        for (int p = ((int)blockIdx.x - b.nbuckets) * kSortBlock + tid; p < ns; p += stride) {
+            const int i = b.sidx[p];
+            const int k = b.key[i];
+            const int cnt = b.bcount[k];
+            if (cnt <= kSortLds) continue;
+            const int off = b.bq_off[k];
+            const unsigned long long mine = b.skey[p];
+            int rank = 0;
+            for (int q = off; q < off + cnt; ++q) {
+                const unsigned long long o = b.skey[q];
+                rank += (o < mine || (o == mine && b.sidx[q] < i)) ? 1 : 0;
+            }
+            put(off + rank, i);
+        }
+        return;
+    }
+    const int k = blockIdx.x;
+    const int cnt = b.bcount[k];
+    if (cnt <= 0 || cnt > kSortLds) return;
+    const int off = b.bq_off[k];
+    if (cnt <= kCountMax) {
+        for (int p = tid; p < cnt; p += kSortBlock) {
+            s_key[p] = b.skey[off + p];
+            s_idx[p] = b.sidx[off + p];
+        }
+        __syncthreads();
+        for (int p = tid; p < cnt; p += kSortBlock) {
+            const unsigned long long mine = s_key[p];
+            const int i = s_idx[p];
+            int rank = 0;
+#pragma unroll 8
+            for (int q = 0; q < cnt; ++q) {
+                const unsigned long long o = s_key[q];
+                rank += (o < mine || (o == mine && s_idx[q] < i)) ? 1 : 0;
+            }
+            put(off + rank, i);
+        }
+        return;
+    }
+    int P = kSortBlock;
+    while (P < cnt) P <<= 1;
+    switch (P / kSortBlock) {
+    case 1: bitonic_block<1>(b, off, cnt, s_key, s_idx, put); break;
+    case 2: bitonic_block<2>(b, off, cnt, s_key, s_idx, put); break;
+    case 4: bitonic_block<4>(b, off, cnt, s_key, s_idx, put); break;
+    default: bitonic_block<8>(b, off, cnt, s_key, s_idx, put); break;
+    }
+}
+
+// Run-start flags of the sorted order (one byte per position: 1 where the
+// candidate range differs from the previous position's; positions past the
+// segments with candidates, up to the next multiple of 16, get 0).
+__global__ void k_gs_flags(DevBatch b, GreedyBufs g, int n16) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n16) return;
     const int nv = (int)b.ctr->n_sorted;
     uint8_t flag = 0;
-    if (p < nv) {
-        const int i = g.vout[p];
-        const int f = b.first[i], l = b.last[i];
-        b.perm[p] = i;
-        b.first_s[p] = f;
-        b.last_s[p] = l;
-        flag = 1;
-        if (p > 0) {
-            const int j = g.vout[p - 1];
-            flag = (f != b.first[j] || l != b.last[j]) ? 1 : 0;
-        }
-    }
+    if (p < nv)
+        flag = (p == 0 || b.first_s[p] != b.first_s[p - 1] || b.last_s[p] != b.last_s[p - 1]) ? 1 : 0;
     g.flag[p] = flag;
 }
 
@@ -351,14 +419,22 @@ __global__ __launch_bounds__(kChainBlock) void k_gs_unit_scan(DevBatch b, Greedy
 
 }  // namespace
 
+hipError_t launch_bucket_sort(DevBatch b, hipStream_t st) {
+    const int nq = b.nq;
+    if (nq <= 0 || !b.skey || !b.sidx) return hipErrorInvalidValue;
+    // big-bin blocks only where a bin can exceed the LDS sort
+    const int need = (nq + kSortBlock - 1) / kSortBlock;
+    const int big = nq > kSortLds ? (need < 1024 ? need : 1024) : 0;
+    hipLaunchKernelGGL(k_gs_bin_sort, dim3(b.nbuckets + big), dim3(kSortBlock), 0, st, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_greedy(DevBatch b, GreedyBufs g, int bound, int is_max, hipStream_t st) {
     const int nq = b.nq;
     if (nq <= 0) return hipErrorInvalidValue;  // the caller skips an empty batch
     const int blk = 256;
     const int n16 = (nq + 15) & ~15;
-    hipLaunchKernelGGL(k_gs_bin_sort, dim3(b.nbuckets), dim3(kSortBlock), 0, st, b, g);
-    hipLaunchKernelGGL(k_gs_rank_big, dim3((nq + blk - 1) / blk), dim3(blk), 0, st, b, g);
-    hipLaunchKernelGGL(k_gs_place, dim3((n16 + blk - 1) / blk), dim3(blk), 0, st, b, g, n16);
+    hipLaunchKernelGGL(k_gs_flags, dim3((n16 + blk - 1) / blk), dim3(blk), 0, st, b, g, n16);
     hipLaunchKernelGGL(k_gs_chain, dim3(1), dim3(kChainBlock), 0, st, b, g, bound, is_max);
     hipLaunchKernelGGL(k_gs_tiles, dim3(kTileGrid), dim3(blk), 0, st, b, g);
     hipLaunchKernelGGL(k_gs_unit_scan, dim3(1), dim3(kChainBlock), 0, st, b, g);

@@ -44,6 +44,17 @@ __host__ __device__ inline int chunk_entries(int ne, int nchunk) {
     return (per + 63) & ~63;
 }
 
+// Segments of one t_start bin sorted in LDS by the bin sort; larger bins are
+// ranked by counting over global memory.
+constexpr int kSortLds = 2048;
+
+// Unsigned bits of a binary64 value that order as the value does (-0 as +0).
+__device__ __forceinline__ unsigned long long start_bits(double x) {
+    x = x + 0.0;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
 // The pair kernel splits a batch over its waves by cost rather than by work
 // units (query segment x entry chunk): a pass over one chunk of a tile costs
 // its nq segments plus a fixed overhead (loading the chunk and staging the
@@ -116,7 +127,7 @@ struct Counters {
     unsigned int err;            // bit 0: invalid query segment
     unsigned int n_tiles;
     unsigned int n_sorted;       // query segments placed in tiles
-    unsigned int pad;
+    unsigned int big_bins;       // t_start bins with more than kSortLds segments (sorted tilings)
     unsigned long long spill;    // spill slabs taken by the pair kernel (may exceed nslabs - nwaves)
     unsigned long long n_slabs;  // slabs in use after the refine
 };
@@ -174,6 +185,11 @@ struct DevBatch {
     long long *units;           // per tile (periodic)
     long long *unit_off;        // exclusive scan of units per tile (+ total)
     long long *cost_off;        // exclusive scan of tile costs (+ total)
+    // Sorted tilings (Periodic, greedy): the counting sort writes each
+    // segment's order key here by bucket position instead of perm, and the
+    // bin sort places it exactly; null for range tiling.
+    unsigned long long *skey;   // order bits of t_start [nq]
+    int32_t *sidx;              // caller index [nq]
     Counters *ctr;
 };
 
@@ -192,8 +208,8 @@ enum : int { kTilePeriodic = 0, kTileRange = 1, kTileGreedyMin = 2, kTileGreedyM
 
 // Work arrays of the GreedySetSplit tiling (nq = query segments of the batch).
 struct GreedyBufs {
-    unsigned long long *kin;         // t_start order bits, bin order (large bins) [nq]
-    int32_t *vout;                   // caller indices in (t_start, caller index) order [nq]
+    unsigned long long *kin;         // DevBatch::skey [nq]
+    int32_t *vout;                   // DevBatch::sidx [nq]
     uint8_t *flag;                   // run start by sorted position [nq rounded up to 16]
     int32_t *gpos;                   // first sorted position of each run (group) [nq + 1]
     int32_t *jump;                   // levels x stride: the 2^k-th next batch start
@@ -231,9 +247,14 @@ hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
 // Trajectory merge (tds_traj.hip): temp bytes for n hits, and the launch
 // (n > 0 hits; writes the merged records to `out` and their number to *total).
 size_t traj_temp_bytes(long long n);
-// GreedySetSplit tiles (after launch_prepare with a greedy tiling): orders
-// the query segments with candidates, builds the runs, the batch chain and
-// the tiles, and scans the work units.
+// Exact (t_start, caller index) order of the bucketed query segments (after
+// launch_prepare with a Periodic or greedy tiling, b.skey / b.sidx set):
+// perm, first_s and last_s in that order (tds_greedy.hip).
+hipError_t launch_bucket_sort(DevBatch b, hipStream_t st);
+// Periodic tiles over the sorted order and their unit and cost offsets.
+hipError_t launch_periodic(DevBatch b, hipStream_t st);
+// GreedySetSplit tiles (after launch_bucket_sort): builds the runs, the
+// batch chain and the tiles, and scans the work units.
 hipError_t launch_greedy(DevBatch b, GreedyBufs g, int bound, int is_max, hipStream_t st);
 hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
                              const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,

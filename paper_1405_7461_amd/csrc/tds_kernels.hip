@@ -283,7 +283,7 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
                 key = j1 * kSpanClasses + cls;
                 if (cls == kSpanClasses - 1) kj2 = j2;
             }
-        } else if (b.tiling == kTilePeriodic || any) {  // greedy: segments with candidates
+        } else if (any) {  // Periodic and greedy: segments with candidates, by t_start bin
             double u = floor((s0 - ix.t_first) / ix.width);
             key = u <= 0.0 ? 0 : (u >= (double)(b.nbuckets - 1) ? b.nbuckets - 1 : (int)u);
         }
@@ -425,6 +425,7 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
         int c, e0, ne;
         get(r, &c, &e0, &ne);
         c_sum += c;
+        if (!range && c > kSortLds) atomicAdd(&b.ctr->big_bins, 1u);
         if (range && c > 0) {
             const int nch = (ne + b.chunk - 1) / b.chunk;
             t_sum += 1;
@@ -502,19 +503,27 @@ __global__ void k_scatter(DevBatch b) {
     int k = b.key[i];
     if (k < 0) return;
     int pos = b.bq_off[k * kBucketSub + (i % kBucketSub)] + b.qrank[i];
+    if (b.skey) {  // sorted tilings: the order key, for the bin sort
+        b.skey[pos] = start_bits(b.rec[i].t0);
+        b.sidx[pos] = i;
+        return;
+    }
     b.perm[pos] = i;
     b.first_s[pos] = b.first[i];
     b.last_s[pos] = b.last[i];
 }
 
-// Periodic tiles (Sec. 6): one wave per tile of s consecutive sorted query
-// segments; the tile's range is the union of its members' ranges.
+// Periodic tiles (Sec. 6): one wave per tile of s consecutive query segments
+// in (t_start, caller index) order; the tile's range is the union of its
+// members' ranges.
 __global__ void k_periodic_tiles(DevBatch b) {
     const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (t >= b.ntiles_cap) return;
     const int q0 = t * b.s;
-    const int nq = min(b.s, b.nq - q0);
+    // tiles past the sorted segments (those without candidates are not
+    // placed) stay empty
+    const int nq = max(0, min(b.s, (int)b.ctr->n_sorted - q0));
     int lo = 0x7fffffff, hi = -1;
     for (int k = lane; k < nq; k += 64) {
         int f = b.first_s[q0 + k], l = b.last_s[q0 + k];
@@ -538,20 +547,24 @@ __global__ void k_periodic_tiles(DevBatch b) {
         tl.pad0 = tl.pad1 = 0;
         b.tiles[t] = tl;
         b.units[t] = (long long)tl.nchunk * nq;
-        if (tl.ne > 0) atomicAdd(&b.ctr->n_eval, (unsigned long long)nq * (unsigned long long)tl.ne);
     }
 }
 
-// One block: exclusive scans of the periodic tiles' work units and costs.
+// One block: exclusive scans of the periodic tiles' work units and costs,
+// and their interactions (n_eval).
 __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
     const int n = b.ntiles_cap;
     const int per = (n + kScanBlock - 1) / kScanBlock;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
     long long s = 0, k_sum = 0;
+    unsigned long long ev = 0;
     for (int k = lo; k < hi; ++k) {
         s += b.units[k];
         k_sum += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
+        ev += (unsigned long long)b.tiles[k].nq * (unsigned long long)b.tiles[k].ne;
     }
+    ev = wave_sum_u64(ev);
+    if (lane_id() == 0 && ev) atomicAdd(&b.ctr->n_eval, ev);
     long long tot, k_tot;
     long long run = block_exclusive_scan<kScanBlock>(s, &tot);
     long long k_run = block_exclusive_scan<kScanBlock>(k_sum, &k_tot);
@@ -562,7 +575,8 @@ __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
         k_run += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
     }
     if (threadIdx.x == 0) {
-        b.ctr->n_tiles = (unsigned)n;
+        // empty tiles come last and add no units or cost
+        b.ctr->n_tiles = (b.ctr->n_sorted + (unsigned)b.s - 1) / (unsigned)b.s;
         b.ctr->n_units = (unsigned long long)tot;
         b.unit_off[n] = tot;
         b.cost_off[n] = k_tot;
@@ -582,11 +596,14 @@ hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, D
                        q[6], q[7], d, b, ix);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanBlock), 0, st, b, ix);
     hipLaunchKernelGGL(k_scatter, dim3(qgrid), dim3(blk), 0, st, b);
-    if (b.tiling == kTilePeriodic) {
-        int waves = b.ntiles_cap;
-        hipLaunchKernelGGL(k_periodic_tiles, dim3((waves * 64 + blk - 1) / blk), dim3(blk), 0, st, b);
-        hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kScanBlock), 0, st, b);
-    }
+    TDS_LAUNCH_CHECK();
+}
+
+hipError_t launch_periodic(DevBatch b, hipStream_t st) {
+    const int blk = 256;
+    const int waves = b.ntiles_cap;
+    hipLaunchKernelGGL(k_periodic_tiles, dim3((waves * 64 + blk - 1) / blk), dim3(blk), 0, st, b);
+    hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kScanBlock), 0, st, b);
     TDS_LAUNCH_CHECK();
 }
 

@@ -152,9 +152,9 @@ def workload_terms(index: "api.Index", q, tiling="range", batch_size: int = 128)
     a batch, on the host from the index's bins (no kernel runs).
 
     range tiling: each segment meets its own candidate range. Periodic:
-    consecutive runs of batch_size segments in t_start order meet the hull of
-    their members' ranges (the device's order within a t_start bin may
-    differ, so this is the model's estimate of its interactions).
+    consecutive runs of batch_size segments with candidates, in (t_start,
+    caller index) order as the device walks them, meet the hull of their
+    members' ranges.
     """
     t0 = np.asarray(q.t0, dtype=np.float64)
     t1 = np.asarray(q.t1, dtype=np.float64)
@@ -164,13 +164,11 @@ def workload_terms(index: "api.Index", q, tiling="range", batch_size: int = 128)
     active = size > 0
     if tiling == "periodic":
         order = np.argsort(t0, kind="stable")
+        order = order[active[order]]
         seg_int = np.zeros_like(size)
         for s in range(0, order.size, batch_size):
             grp = order[s:s + batch_size]
-            ok = grp[active[grp]]
-            if ok.size:
-                hull = last[ok].max() - first[ok].min() + 1
-                seg_int[grp] = hull
+            seg_int[grp] = last[grp].max() - first[grp].min() + 1
         interactions = float(seg_int.sum())
         n_tiles = -(-order.size // batch_size)
     else:

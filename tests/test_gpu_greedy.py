@@ -1,4 +1,5 @@
-"""GreedySetSplit tiles (Sec. 6, Alg. 4) on the GPU against the oracle's batches.
+"""GreedySetSplit and Periodic tiles (Sec. 6, Alg. 4) on the GPU against the
+oracle's batches.
 
 * Fig. 2 on the device: batch sizes and interactions of the hand-worked
   golden (tests/golden/fig2_greedy.txt) for both variants;
@@ -8,6 +9,10 @@
   the oracle's search;
 * full-size C4 (uneven queries with per-trajectory d): tiles identical to
   the oracle's, every hit confirmed pair by pair, a sampled oracle search;
+* Periodic tiles identical to the oracle's (runs of s segments with
+  candidates in (t_start, caller index) order) on the same cases and on
+  full-size C4, whose short query trajectories at arbitrary times make the
+  order within a t_start bin matter;
 * edge cases: no segment with candidates, bound 1, bound >= |Q|, t_start
   bins holding more query segments than one workgroup sorts in LDS.
 """
@@ -24,18 +29,21 @@ from gpu_util import compare, say
 
 pytestmark = pytest.mark.gpu
 VARIANTS = {"min": "greedy_min", "max": "greedy_max"}
+TILINGS = dict(VARIANTS, periodic="periodic")
 
 
 def _oracle_batches(db, q, m, bound, variant):
     o = ob.entry_order(db.t0)
     bins = ob.bin_table(db.t0[o], db.t1[o], m)
+    if variant == "periodic":
+        return bins, ob.periodic(bins, q.t0, q.t1, bound)
     return bins, ob.greedy_set_split(bins, q.t0, q.t1, bound, variant)
 
 
 def _device(ix, q, variant, bound, mode="fp32_refine"):
     qh = tds.Query(ix)
     try:
-        qh.batch(q, q.d, mode=mode, tiling=VARIANTS[variant], batch_size=bound)
+        qh.batch(q, q.d, mode=mode, tiling=TILINGS[variant], batch_size=bound)
         h = qh.fetch().sorted()
         st = qh.stats()
         tiles, members = qh.tiles()
@@ -115,6 +123,35 @@ def test_tiles_and_hits_match_oracle(variant):
             ix.close()
 
 
+def test_periodic_tiles_match_oracle():
+    for label, (db, q, m) in _cases():
+        want_hits = oracle.search(db, q)
+        ix = tds.build_index(db, m)
+        try:
+            for s in (1, 7, 128, 5000):
+                h, st, tiles, members = _device(ix, q, "periodic", s)
+                bins, want = _oracle_batches(db, q, m, s, "periodic")
+                _compare_tiles(bins, want, tiles, members, st, f"{label} periodic {s}")
+                compare(h, want_hits, db, f"{label} periodic {s}")
+                say(f"{label} periodic {s}: {len(want)} tiles, n_eval {st['n_eval']}, {len(h)} hits")
+        finally:
+            ix.close()
+
+
+def test_full_size_c4_periodic_tiles():
+    db = gen.make_db("C4")
+    q = gen.make_queries("C4")
+    ix = tds.build_index(db, 1000)
+    try:
+        for s in (64, 128):
+            h, st, tiles, members = _device(ix, q, "periodic", s)
+            bins, want = _oracle_batches(db, q, 1000, s, "periodic")
+            _compare_tiles(bins, want, tiles, members, st, f"C4 full periodic {s}")
+            say(f"C4 full periodic {s}: {len(want)} tiles, n_eval {st['n_eval']}, {len(h)} hits")
+    finally:
+        ix.close()
+
+
 def test_full_size_c4_tiles():
     from test_gpu_fullsize import _check_hits_one_by_one, _check_sample
     db = gen.make_db("C4")
@@ -141,7 +178,7 @@ def test_edge_cases():
         far = q.subset(np.arange(len(q)))
         far.t0 = far.t0 + 1e6
         far.t1 = far.t1 + 1e6
-        for v in VARIANTS:
+        for v in TILINGS:
             h, st, tiles, members = _device(ix, far, v, 16)
             assert len(h) == 0 and len(tiles) == 0 and len(members) == 0 and st["n_eval"] == 0
             h, st, tiles, _ = _device(ix, q, v, 1 << 16)

@@ -76,6 +76,25 @@ def test_beta_device_host_oracle():
     ix.close()
 
 
+def test_periodic_interactions_host_equals_device():
+    """The model's Periodic interactions follow the device's order exactly,
+    also where query segments of one t_start bin have different ends (C4)."""
+    db = gen.make_db("C4", ntraj=300)
+    q = gen.make_queries("C4", nq=24)
+    ix = tds.build_index(db, 1000)
+    qh = tds.Query(ix)
+    try:
+        for s in (1, 7, 64, 1000):
+            qh.batch(q, q.d, mode="fp32_refine", tiling="periodic", batch_size=s)
+            qh.fetch()
+            st = qh.stats()
+            w = M.workload_terms(ix, q, tiling="periodic", batch_size=s)
+            assert w["interactions"] == st["n_eval"] and w["n_tiles"] == st["n_tiles"], s
+    finally:
+        qh.close()
+        ix.close()
+
+
 def test_calibrate_alpha_predict():
     t0 = time.perf_counter()
     model = M.calibrate(qs=(16, 256, 2048), cs=(256, 4096), reps=2, log=say)
