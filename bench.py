@@ -439,8 +439,8 @@ def main():
                          "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library does not "
+              "shard a search across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
