@@ -529,14 +529,16 @@ static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, 
     const size_t n = (size_t)nq, n1 = n + 1;
     // 8-byte arrays first: kin, tev; then the 4-byte ones, then the flags
     const size_t n16 = (n + 15) & ~(size_t)15;
-    const size_t bytes = n * 8 * 2 + n * 4 + n1 * 4 * 3 + 2 * 4 + n16 + 64;
+    const size_t bytes = n * 8 * 3 + n * 4 * 2 + n1 * 4 * 3 + 2 * 4 + n16 + 64;
     HIP_TRY(q->gs_work.ensure(bytes));
     if (chain) HIP_TRY(q->gs_jump.ensure((size_t)levels * n1 * 4));
     char *w = q->gs_work.as<char>();
     auto take = [&](size_t b) { char *p = w; w += b; return p; };
     g->kin = (unsigned long long *)take(n * 8);
+    g->tkey = (unsigned long long *)take(n * 8);
     g->tev = (long long *)take(n * 8);
     g->vout = (int32_t *)take(n * 4);
+    g->tidx = (int32_t *)take(n * 4);
     g->gpos = (int32_t *)take(n1 * 4);
     g->mark = (int32_t *)take(n1 * 4);
     g->gb = (int32_t *)take(n1 * 4);
@@ -709,13 +711,15 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
     const bool sorted = greedy || o.tiling == TDS_TILE_PERIODIC;
     GreedyBufs gb{};
-    b.skey = nullptr;
-    b.sidx = nullptr;
+    b.skey = b.tkey = nullptr;
+    b.sidx = b.tidx = nullptr;
     if (sorted && nq > 0) {
         rc = greedy_buffers(q, nq, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, greedy, &gb);
         if (rc) return rc;
         b.skey = gb.kin;
         b.sidx = gb.vout;
+        b.tkey = gb.tkey;
+        b.tidx = gb.tidx;
     }
 
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;

@@ -40,11 +40,12 @@ namespace {
 // nbuckets take one bin of at most kSortLds segments each and rank it in
 // LDS: by counting (broadcast reads) up to kCountMax segments, by a bitonic
 // network above (counting is quadratic: at 512 segments it took 65 us on a
-// batch where the network takes 23 us). The blocks after them rank the members of larger bins by
-// counting over global memory, a grid-stride loop over positions (these bins
-// are rare; k_bucket_scan counts them, and with none the blocks return at
-// once). Reads go to skey / sidx only and writes to perm, first_s, last_s
-// only, so no block sees another's writes.
+// batch where the network takes 23 us). The blocks after them, one per
+// window of kSortLds positions, sort the pieces of larger bins into tkey /
+// tidx for k_gs_merge_big (such bins are rare; k_bucket_scan counts them,
+// and with none these blocks return at once). Reads go to skey / sidx only
+// and writes to perm, first_s, last_s, tkey, tidx only, so no block sees
+// another's writes.
 constexpr int kSortBlock = 256;
 #ifndef TDS_COUNT_MAX
 #define TDS_COUNT_MAX 64
@@ -130,7 +131,7 @@ __device__ void bitonic_block(const DevBatch &b, int off, int cnt, unsigned long
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const int p = k * kSortBlock + tid;
-        if (p < cnt) put(off + p, idx[k]);
+        if (p < cnt) put(off + p, key[k], idx[k]);
     }
 }
 
@@ -143,23 +144,35 @@ __global__ __launch_bounds__(kSortBlock) void k_gs_bin_sort(DevBatch b) {
         b.first_s[p] = b.first[i];
         b.last_s[p] = b.last[i];
     };
-    if ((int)blockIdx.x >= b.nbuckets) {  // members of bins too large for LDS
+    auto put3 = [&](int p, unsigned long long, int i) { put(p, i); };
+    if ((int)blockIdx.x >= b.nbuckets) {
+        // Bins too large for LDS: window w of kSortLds positions sorts its
+        // piece of each such bin it meets (at most two) into tkey / tidx at
+        // the same positions; k_gs_merge_big then ranks across pieces.
         if (b.ctr->big_bins == 0) return;
         const int ns = (int)b.ctr->n_sorted;
-        const int stride = ((int)gridDim.x - b.nbuckets) * kSortBlock;
-        for (int p = ((int)blockIdx.x - b.nbuckets) * kSortBlock + tid; p < ns; p += stride) {
-            const int i = b.sidx[p];
-            const int k = b.key[i];
-            const int cnt = b.bcount[k];
-            if (cnt <= kSortLds) continue;
-            const int off = b.bq_off[k];
-            const unsigned long long mine = b.skey[p];
-            int rank = 0;
-            for (int q = off; q < off + cnt; ++q) {
-                const unsigned long long o = b.skey[q];
-                rank += (o < mine || (o == mine && b.sidx[q] < i)) ? 1 : 0;
+        const int w0 = ((int)blockIdx.x - b.nbuckets) * kSortLds;
+        const int wend = min(ns, w0 + kSortLds);
+        auto keep = [&](int p, unsigned long long kk, int i) {
+            b.tkey[p] = kk;
+            b.tidx[p] = i;
+        };
+        for (int p0 = w0; p0 < wend;) {
+            const int k = b.key[b.sidx[p0]];
+            const int cnt = b.bcount[k], off = b.bq_off[k];
+            const int pend = min(wend, off + cnt);
+            if (cnt > kSortLds) {
+                const int len = pend - p0;
+                int P = kSortBlock;
+                while (P < len) P <<= 1;
+                switch (P / kSortBlock) {
+                case 1: bitonic_block<1>(b, p0, len, s_key, s_idx, keep); break;
+                case 2: bitonic_block<2>(b, p0, len, s_key, s_idx, keep); break;
+                case 4: bitonic_block<4>(b, p0, len, s_key, s_idx, keep); break;
+                default: bitonic_block<8>(b, p0, len, s_key, s_idx, keep); break;
+                }
             }
-            put(off + rank, i);
+            p0 = pend;
         }
         return;
     }
@@ -189,10 +202,46 @@ __global__ __launch_bounds__(kSortBlock) void k_gs_bin_sort(DevBatch b) {
     int P = kSortBlock;
     while (P < cnt) P <<= 1;
     switch (P / kSortBlock) {
-    case 1: bitonic_block<1>(b, off, cnt, s_key, s_idx, put); break;
-    case 2: bitonic_block<2>(b, off, cnt, s_key, s_idx, put); break;
-    case 4: bitonic_block<4>(b, off, cnt, s_key, s_idx, put); break;
-    default: bitonic_block<8>(b, off, cnt, s_key, s_idx, put); break;
+    case 1: bitonic_block<1>(b, off, cnt, s_key, s_idx, put3); break;
+    case 2: bitonic_block<2>(b, off, cnt, s_key, s_idx, put3); break;
+    case 4: bitonic_block<4>(b, off, cnt, s_key, s_idx, put3); break;
+    default: bitonic_block<8>(b, off, cnt, s_key, s_idx, put3); break;
+    }
+}
+
+// Ranks of the members of bins too large for LDS (after k_gs_bin_sort sorted
+// their pieces, one per window of kSortLds positions): a member's place in
+// its bin is its index in its own sorted piece plus, for every other piece of
+// the bin, the number of that piece's keys below it (a binary search), so a
+// bin of n segments costs n (n / kSortLds) log2(kSortLds) reads rather than
+// n^2. Returns at once when there are no such bins.
+__global__ void k_gs_merge_big(DevBatch b) {
+    if (b.ctr->big_bins == 0) return;
+    const int ns = (int)b.ctr->n_sorted;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < ns; p += gridDim.x * blockDim.x) {
+        const int k = b.key[b.sidx[p]];  // positions keep their bin in both orders
+        const int cnt = b.bcount[k];
+        if (cnt <= kSortLds) continue;
+        const int off = b.bq_off[k], end = off + cnt;
+        const unsigned long long mine = b.tkey[p];
+        const int i = b.tidx[p];
+        const int wp = p / kSortLds;
+        int rank = p - max(off, wp * kSortLds);
+        for (int w = off / kSortLds; w * kSortLds < end; ++w) {
+            if (w == wp) continue;
+            int lo = max(off, w * kSortLds), hi = min(end, (w + 1) * kSortLds);
+            const int base = lo;
+            while (lo < hi) {  // first key of the piece above mine
+                const int mid = (lo + hi) >> 1;
+                const unsigned long long o = b.tkey[mid];
+                if (o < mine || (o == mine && b.tidx[mid] < i)) lo = mid + 1; else hi = mid;
+            }
+            rank += lo - base;
+        }
+        const int q = off + rank;
+        b.perm[q] = i;
+        b.first_s[q] = b.first[i];
+        b.last_s[q] = b.last[i];
     }
 }
 
@@ -423,9 +472,13 @@ hipError_t launch_bucket_sort(DevBatch b, hipStream_t st) {
     const int nq = b.nq;
     if (nq <= 0 || !b.skey || !b.sidx) return hipErrorInvalidValue;
     // big-bin blocks only where a bin can exceed the LDS sort
-    const int need = (nq + kSortBlock - 1) / kSortBlock;
-    const int big = nq > kSortLds ? (need < 1024 ? need : 1024) : 0;
-    hipLaunchKernelGGL(k_gs_bin_sort, dim3(b.nbuckets + big), dim3(kSortBlock), 0, st, b);
+    // one workgroup per window of kSortLds positions for bins larger than that
+    const int wins = nq > kSortLds ? (nq + kSortLds - 1) / kSortLds : 0;
+    hipLaunchKernelGGL(k_gs_bin_sort, dim3(b.nbuckets + wins), dim3(kSortBlock), 0, st, b);
+    if (wins > 0) {
+        const int need = (nq + kSortBlock - 1) / kSortBlock;
+        hipLaunchKernelGGL(k_gs_merge_big, dim3(need < 1024 ? need : 1024), dim3(kSortBlock), 0, st, b);
+    }
     return hipGetLastError();
 }
 

@@ -190,6 +190,8 @@ struct DevBatch {
     // bin sort places it exactly; null for range tiling.
     unsigned long long *skey;   // order bits of t_start [nq]
     int32_t *sidx;              // caller index [nq]
+    unsigned long long *tkey;   // pieces of bins too large for LDS, sorted [nq]
+    int32_t *tidx;              // ... their caller indices [nq]
     Counters *ctr;
 };
 
@@ -210,6 +212,8 @@ enum : int { kTilePeriodic = 0, kTileRange = 1, kTileGreedyMin = 2, kTileGreedyM
 struct GreedyBufs {
     unsigned long long *kin;         // DevBatch::skey [nq]
     int32_t *vout;                   // DevBatch::sidx [nq]
+    unsigned long long *tkey;        // DevBatch::tkey [nq]
+    int32_t *tidx;                   // DevBatch::tidx [nq]
     uint8_t *flag;                   // run start by sorted position [nq rounded up to 16]
     int32_t *gpos;                   // first sorted position of each run (group) [nq + 1]
     int32_t *jump;                   // levels x stride: the 2^k-th next batch start
