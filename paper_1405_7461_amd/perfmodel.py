@@ -95,6 +95,7 @@ class PerfModel:
     t_first: float = 0.0
     t_last: float = 1.0
     tile_ms: float = 0.0                     # cost of one more tile in the launch
+    sort_ms: Tuple[float, float] = (0.0, 0.0)  # a + b q: the t_start sort of Periodic and greedy
 
     # Sec. 8.1
     def gpu_ms(self, alpha: float, beta: float, i: float, c: float) -> float:
@@ -125,6 +126,9 @@ class PerfModel:
         # launch costs tile_ms (the counterpart of the paper's per-invocation
         # overhead summed over batches)
         g += self.tile_ms * max(w["n_tiles"] - 1, 0)
+        # Periodic and the greedy tilings also sort their segments by t_start
+        if tiling != "range":
+            g += max(0.0, self.sort_ms[0] + self.sort_ms[1] * w["q_active"])
         cpu = self.cpu.ms(len(q.t0), hits * HIT_BYTES_HOST, host_inputs, host_output)
         return dict(ms=g + cpu, gpu_ms=g, cpu_ms=cpu, alpha=alpha, beta=beta, gamma=1 - alpha - beta,
                     interactions=i, c=c, expected_hits=hits, n_tiles=w["n_tiles"])
@@ -134,7 +138,8 @@ class PerfModel:
              for k, v in self.tables.items()}
         return json.dumps(dict(tables=t, cpu=self.cpu.__dict__,
                                alpha=None if self.alpha is None else list(map(float, self.alpha)),
-                               t_first=self.t_first, t_last=self.t_last, tile_ms=self.tile_ms))
+                               t_first=self.t_first, t_last=self.t_last, tile_ms=self.tile_ms,
+                               sort_ms=list(self.sort_ms)))
 
     @staticmethod
     def from_json(s: str) -> "PerfModel":
@@ -142,7 +147,8 @@ class PerfModel:
         t = {k: {float(c): (np.array(x), np.array(y)) for c, (x, y) in v.items()}
              for k, v in d["tables"].items()}
         return PerfModel(t, CpuFit(**d["cpu"]), None if d["alpha"] is None else np.array(d["alpha"]),
-                         d["t_first"], d["t_last"], d.get("tile_ms", 0.0))
+                         d["t_first"], d["t_last"], d.get("tile_ms", 0.0),
+                         tuple(d.get("sort_ms", (0.0, 0.0))))
 
 
 # ------------------------------------------------- interactions and beta
@@ -311,22 +317,62 @@ def calibrate(qs: Sequence[int] = (256, 2048, 16384, 131072),
         ix.close()
     bw = _d2h_bandwidth()
     tile_ms = _tile_cost(opts, rng, reps)
+    sort_ms = _sort_cost(opts, rng, reps)
     out = {k: {c: (np.array(x), np.array(y)) for c, (x, y) in v.items()} for k, v in tables.items()}
-    return PerfModel(out, CpuFit(a, b, e, bw), tile_ms=tile_ms)
+    return PerfModel(out, CpuFit(a, b, e, bw), tile_ms=tile_ms, sort_ms=sort_ms)
+
+
+def _sort_cost(opts: Dict, rng, reps: int, qs: Sequence[int] = (16384, 131072),
+               m: int = 1024) -> Tuple[float, float]:
+    """Extra preparation of the tilings that sort by t_start: query segments
+    spread over m t_start bins (entries one per unit of time, far from every
+    query: no hits), the preparation stage's event time under Periodic minus
+    that under range tiling, as a + b q through the two query counts."""
+    import torch
+    k = np.arange(m, dtype=np.float64)
+    far = 1000.0 + 10.0 * k
+    z = np.zeros(m)
+    ix = api.build_index(_segments(far, z, z, k, far, z, z, k + 1.0, np.ones(m)), m)
+    qh = api.Query(ix)
+    stream = torch.cuda.current_stream()
+    try:
+        diff = []
+        for q in qs:
+            t0 = rng.uniform(0.0, m - 1.0, size=q)
+            p = rng.uniform(-0.05, 0.05, size=(q, 3))
+            dq = _to_device(_segments(p[:, 0], p[:, 1], p[:, 2], t0, p[:, 0], p[:, 1], p[:, 2], t0 + 0.5,
+                                      np.ones(q)))
+            prep = {}
+            for tiling in ("range", "periodic"):
+                ts = []
+                for r in range(reps + 1):
+                    qh.batch(dq, dq.d, stream=stream, timing=True, **dict(opts, tiling=tiling, batch_size=128))
+                    qh.fetch(out="device")
+                    if r:
+                        ts.append(qh.stats()["ms_prep"])
+                prep[tiling] = float(np.median(ts))
+            diff.append(prep["periodic"] - prep["range"])
+        b = (diff[1] - diff[0]) / (qs[1] - qs[0])
+        return (diff[0] - b * qs[0], b)
+    finally:
+        qh.close()
+        ix.close()
 
 
 def _tile_cost(opts: Dict, rng, reps: int, q: int = 131072, c: int = 1024) -> float:
     """Cost of one more tile: spatial-miss batches whose segments share one
-    range, as one tile (range tiling) and cut into q / s Periodic tiles."""
+    range, cut into q / s Periodic tiles, against the same batch in the
+    fewest Periodic tiles (the same preparation, sort included)."""
     ix = api.build_index(_entries("near", c, rng), 1)
     qh = api.Query(ix)
     try:
         dq = _to_device(_queries("smiss", q, rng))
-        base, _ = _time_call(qh, dq, dict(opts, tiling="range"), reps)
+        s_max = 65536
+        base, _ = _time_call(qh, dq, dict(opts, tiling="periodic", batch_size=s_max), reps)
         xs, ys = [], []
         for s in (16, 64, 256, 1024):
             ms, _ = _time_call(qh, dq, dict(opts, tiling="periodic", batch_size=s), reps)
-            xs.append(float(-(-q // s) - 1))
+            xs.append(float(-(-q // s) - -(-q // s_max)))
             ys.append(ms - base)
         xs, ys = np.array(xs), np.array(ys)
         return max(float(np.dot(xs, ys) / np.dot(xs, xs)), 0.0)  # slope through the origin
