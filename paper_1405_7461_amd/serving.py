@@ -21,6 +21,7 @@ pair kernel with a larger buffer.
 from __future__ import annotations
 
 import collections
+import gc
 import queue
 import threading
 import time
@@ -145,11 +146,20 @@ class Server:
         r.est_bytes = HIT_BYTES * self.k_safety * max(1.0, self.alpha.expected_hits(r.seg.t0, r._n_eval_seg))
 
     # -------------------------------------------------------------- running
-    def warmup(self, requests: Sequence[Request]) -> None:
+    def warmup(self, requests: Sequence[Request], reserve_segments: int = 0) -> None:
         """Run the requests once on every executor, untimed and unrecorded.
 
         Grows each query handle's device buffers to the sizes these requests
-        need, so that a measured run does not pay first-use allocations.
+        need, so that a measured run does not pay first-use allocations
+        (a buffer that grows is freed with hipFree, which waits for the whole
+        device, the other executors' batches included). With
+        reserve_segments, one more batch repeats the requests' segments up to
+        that many, so batches of up to that size find their buffers grown.
+        Last, the requests are served four times over through the admission
+        loop at staggered arrivals, so that the worker threads' first calls
+        into the runtime also happen here: a first measured run otherwise
+        showed fetches of 6-7 ms on small batches that later runs in the same
+        process did not.
         The hit-rate estimates learnt here are kept; the batch log is not.
         """
         for ex in self.executors:
@@ -162,10 +172,34 @@ class Server:
             if requests:
                 seg, d = _concat(list(requests))
                 ex(seg, d, int(self.pool_bytes / HIT_BYTES) + 1024)
+                n = len(d)
+                if reserve_segments > n:
+                    reps = -(-int(reserve_segments) // n)
+                    big = type(seg)()
+                    for f in FIELDS:
+                        setattr(big, f, np.tile(getattr(seg, f), reps)[:reserve_segments])
+                    ex(big, np.tile(d, reps)[:reserve_segments], int(self.pool_bytes / HIT_BYTES) + 1024)
+        if requests:
+            replay = [Request(rid=k, seg=r.seg, d=r.d, arrival=2e-4 * k)
+                      for k, r in enumerate(list(requests) * 4)]
+            self.run(replay)
         self.batches.clear()
 
     def run(self, requests: Sequence[Request], time_scale: float = 1.0) -> Dict:
-        """Serve requests at their arrival times (seconds x time_scale)."""
+        """Serve requests at their arrival times (seconds x time_scale).
+
+        The objects alive at the start are moved out of the garbage
+        collector's generations for the run (gc.freeze), so its collections
+        only walk what the run itself allocates.
+        """
+        gc.collect()
+        gc.freeze()
+        try:
+            return self._run(requests, time_scale)
+        finally:
+            gc.unfreeze()
+
+    def _run(self, requests: Sequence[Request], time_scale: float) -> Dict:
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             self.plan(r)
