@@ -359,6 +359,47 @@ __device__ __forceinline__ long long block_exclusive_scan(long long v, long long
     return before + incl - v;
 }
 
+// Four exclusive scans over the block at once (one value of each per
+// thread): the wave-level steps of the four run side by side and the
+// warp totals of value k are scanned by wave k, so the four cost about one.
+template <int BLOCK>
+__device__ __forceinline__ void block_exclusive_scan4(const long long (&v)[4], long long (&run)[4],
+                                                      long long (&total)[4]) {
+    static_assert(BLOCK / 64 >= 4 && BLOCK / 64 <= 64, "one wave per value, one lane per wave");
+    __shared__ long long warp_sums[4][BLOCK / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    long long incl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) incl[k] = v[k];
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long y = __shfl_up(incl[k], off);
+            if (lane >= off) incl[k] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) warp_sums[k][w] = incl[k];
+    }
+    __syncthreads();
+    if (w < 4) {
+        long long s = lane < BLOCK / 64 ? warp_sums[w][lane] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(s, off);
+            if (lane >= off) s += y;
+        }
+        if (lane < BLOCK / 64) warp_sums[w][lane] = s;  // inclusive over warps
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        total[k] = warp_sums[k][BLOCK / 64 - 1];
+        run[k] = (w > 0 ? warp_sums[k][w - 1] : 0) + incl[k] - v[k];
+    }
+    __syncthreads();
+}
+
 // Candidate range of a range bucket (all its queries share it).
 __device__ __forceinline__ void bucket_range(const DevBatch &b, const DevIndex &ix, int k,
                                              int *e0, int *ne) {
@@ -441,11 +482,12 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
     } else {
         for (int r = 0; r < hi - lo; ++r) tally(r);
     }
-    long long c_tot, t_tot, u_tot, k_tot;
-    long long c_run = block_exclusive_scan<kScanBlock>(c_sum, &c_tot);
-    long long t_run = block_exclusive_scan<kScanBlock>(t_sum, &t_tot);
-    long long u_run = block_exclusive_scan<kScanBlock>(u_sum, &u_tot);
-    long long k_run = block_exclusive_scan<kScanBlock>(k_sum, &k_tot);
+    const long long sums[4] = {c_sum, t_sum, u_sum, k_sum};
+    long long runs[4], tots[4];
+    block_exclusive_scan4<kScanBlock>(sums, runs, tots);
+    long long c_run = runs[0], t_run = runs[1], u_run = runs[2], k_run = runs[3];
+    const long long c_tot = tots[0], t_tot = tots[1], u_tot = tots[2];
+    const long long k_tot = tots[3];
     auto place = [&](int r) {
         const int k = lo + r;
         int c, e0, ne;
@@ -563,11 +605,11 @@ __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
         k_sum += tile_cost(b.tiles[k].nq, b.tiles[k].nchunk, b.pass_cost, b.stage_cost);
         ev += (unsigned long long)b.tiles[k].nq * (unsigned long long)b.tiles[k].ne;
     }
-    ev = wave_sum_u64(ev);
-    if (lane_id() == 0 && ev) atomicAdd(&b.ctr->n_eval, ev);
-    long long tot, k_tot;
-    long long run = block_exclusive_scan<kScanBlock>(s, &tot);
-    long long k_run = block_exclusive_scan<kScanBlock>(k_sum, &k_tot);
+    const long long vals[4] = {s, k_sum, (long long)ev, 0};
+    long long runs[4], tots[4];
+    block_exclusive_scan4<kScanBlock>(vals, runs, tots);
+    long long run = runs[0], k_run = runs[1];
+    const long long tot = tots[0], k_tot = tots[1];
     for (int k = lo; k < hi; ++k) {
         b.unit_off[k] = run;
         b.cost_off[k] = k_run;
@@ -578,6 +620,7 @@ __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
         // empty tiles come last and add no units or cost
         b.ctr->n_tiles = (b.ctr->n_sorted + (unsigned)b.s - 1) / (unsigned)b.s;
         b.ctr->n_units = (unsigned long long)tot;
+        b.ctr->n_eval = (unsigned long long)tots[2];
         b.unit_off[n] = tot;
         b.cost_off[n] = k_tot;
     }
@@ -1058,9 +1101,11 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
     const long long per_w = (sl.nwaves + kScanBlock - 1) / kScanBlock;
     const long long wlo = min((long long)sl.nwaves, (long long)threadIdx.x * per_w);
     const long long whi = min((long long)sl.nwaves, wlo + per_w);
-    long long sum = 0, sel = 0, ovl = 0, tot;
-    if (per <= kScanRun && per_w <= kScanRun) {
-        int h[kScanRun], c[kScanRun];
+    long long sum = 0, sel = 0, ovl = 0;
+    const bool held = per <= kScanRun && per_w <= kScanRun;
+    int h[kScanRun];
+    if (held) {
+        int c[kScanRun];
         unsigned long long o[kScanRun];
 #pragma unroll
         for (int j = 0; j < kScanRun; ++j) {
@@ -1074,7 +1119,20 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
             sel += c[j];
             ovl += (long long)o[j];
         }
-        long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
+    } else {
+        for (long long k = lo; k < hi; ++k) {
+            sum += sl.slab_h[k];
+            sel += sl.slab_n[k];
+        }
+        if (count_ovl)
+            for (long long k = wlo; k < whi; ++k) ovl += (long long)sl.wave_ovl[k];
+    }
+    // hit offsets, selected pairs and overlap counts in one pass of scans
+    const long long vals[4] = {sum, sel, ovl, 0};
+    long long runs[4], tots[4];
+    block_exclusive_scan4<kScanBlock>(vals, runs, tots);
+    long long run = runs[0];
+    if (held) {
 #pragma unroll
         for (int j = 0; j < kScanRun; ++j)
             if (lo + j < hi) {
@@ -1083,20 +1141,11 @@ __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__r
             }
     } else {
         for (long long k = lo; k < hi; ++k) {
-            sum += sl.slab_h[k];
-            sel += sl.slab_n[k];
-        }
-        if (count_ovl)
-            for (long long k = wlo; k < whi; ++k) ovl += (long long)sl.wave_ovl[k];
-        long long run = block_exclusive_scan<kScanBlock>(sum, &tot);
-        for (long long k = lo; k < hi; ++k) {
             sl.hit_off[k] = run;
             run += sl.slab_h[k];
         }
     }
-    long long sel_tot, ovl_tot;
-    (void)block_exclusive_scan<kScanBlock>(sel, &sel_tot);
-    (void)block_exclusive_scan<kScanBlock>(ovl, &ovl_tot);
+    const long long tot = tots[0], sel_tot = tots[1], ovl_tot = tots[2];
     if (threadIdx.x == 0) {
         sl.hit_off[nsl] = tot;
         ctr->hits = (unsigned long long)tot;
