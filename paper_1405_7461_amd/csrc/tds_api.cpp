@@ -900,14 +900,22 @@ int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj
                                hipMemcpyHostToDevice, st));
         qt = q->tr_qtraj.as<int64_t>();
     }
-    // work arrays, 8-byte ones first: qt, et, ta, tb, key_a, key_b, sta, stb,
-    // runmax (9 x 8 B), then idx_a, idx_b, flag, gid, start, mid (6 x 4 B)
+    // work arrays: the whole keys of a small merge (2 x 32 B), then the
+    // 8-byte ones: qt, et, ta, tb, key_a, key_b, sta, stb, runmax (9 x 8 B),
+    // then idx_a, idx_b, flag, gid, start, mid (6 x 4 B)
     const size_t nn = (size_t)n;
-    HIP_TRY(q->tr_work.ensure(nn * (9 * 8 + 6 * 4) + 64));
+    const bool one = n <= kTrajOneSortMax;
+    const size_t kbytes = one ? nn * 2 * sizeof(TrajKey) : 0;
+    HIP_TRY(q->tr_work.ensure(kbytes + nn * (9 * 8 + 6 * 4) + 64));
     char *w = q->tr_work.as<char>();
     auto take8 = [&](void *&dst) { dst = w; w += nn * 8; };
     auto take4 = [&](void *&dst) { dst = w; w += nn * 4; };
     TrajBufs t{};
+    if (one) {
+        t.kin = reinterpret_cast<TrajKey *>(w);
+        t.kout = t.kin + nn;
+        w += kbytes;
+    }
     take8((void *&)t.qt); take8((void *&)t.et); take8((void *&)t.ta); take8((void *&)t.tb);
     take8((void *&)t.key_a); take8((void *&)t.key_b); take8((void *&)t.sta); take8((void *&)t.stb);
     take8((void *&)t.runmax);

@@ -196,6 +196,16 @@ struct DevBatch {
 };
 
 // Work arrays of the trajectory merge (n hits each).
+// One hit of the trajectory merge as a whole sort key (small merges).
+struct TrajKey {
+    int64_t qt, et;
+    double ta, tb;
+};
+
+// Merges of at most this many hits sort TrajKey records once with a
+// comparison merge sort; larger ones use three stable radix sorts.
+constexpr long long kTrajOneSortMax = 1LL << 16;
+
 struct TrajBufs {
     int64_t *qt, *et;                  // trajectory ids, hit order
     double *ta, *tb;                   // interval, hit order
@@ -203,6 +213,7 @@ struct TrajBufs {
     int32_t *idx_a, *idx_b;            // permutations
     int32_t *flag, *gid, *start, *mid; // sorted order: pair start, pair id, run start, record no.
     double *sta, *stb, *runmax;        // sorted order: interval, running maximum of t_b
+    TrajKey *kin, *kout;               // small merges: hit order, sorted order
 };
 
 enum : int { kModeFP64 = 0, kModeFP32Refine = 1 };

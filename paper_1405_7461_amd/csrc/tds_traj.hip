@@ -6,7 +6,9 @@
 // pair are pieces of that answer, and their union is it. Steps: gather the
 // hits with their two trajectory ids, sort by (query trajectory, entry
 // trajectory, t_a) with three stable radix sorts (least significant key
-// first), then one segmented running maximum of t_b marks where a new
+// first; merges of up to kTrajOneSortMax hits instead sort whole 32-byte
+// keys once with a comparison merge sort, a third of the launches), then
+// one segmented running maximum of t_b marks where a new
 // maximal interval starts (its t_a lies after every earlier t_b of the pair;
 // closed intervals that touch merge), and a scan of those marks numbers the
 // output records.
@@ -49,6 +51,7 @@ __global__ __launch_bounds__(256) void k_traj_gather(Slabs sl, const Counters *_
             t.tb[k] = h.tb;
             t.key_a[k] = order_bits(h.ta);
             t.idx_a[k] = (int32_t)k;
+            if (t.kin) t.kin[k] = TrajKey{t.qt[k], t.et[k], h.ta, h.tb};
         }
     }
 }
@@ -75,6 +78,21 @@ __global__ void k_traj_flags(TrajBufs t, const int32_t *__restrict__ idx, long l
     t.stb[i] = t.tb[o];
 }
 
+// The same from the sorted whole keys of a small merge.
+__global__ void k_traj_flags_one(TrajBufs t, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const TrajKey k = t.kout[i];
+    bool start = i == 0;
+    if (!start) {
+        const TrajKey p = t.kout[i - 1];
+        start = k.qt != p.qt || k.et != p.et;
+    }
+    t.flag[i] = start ? 1 : 0;
+    t.sta[i] = k.ta;
+    t.stb[i] = k.tb;
+}
+
 // A maximal interval starts where the pair starts or t_a exceeds the running
 // maximum of the pair's earlier t_b.
 __global__ void k_traj_starts(TrajBufs t, long long n) {
@@ -92,9 +110,14 @@ __global__ void k_traj_emit(TrajBufs t, const int32_t *__restrict__ idx, long lo
     if (i >= n) return;
     const long long m = (long long)t.mid[i] - 1;
     if (t.start[i]) {
-        const int32_t o = idx[i];
-        out[m].query_traj = t.qt[o];
-        out[m].entry_traj = t.et[o];
+        if (idx) {
+            const int32_t o = idx[i];
+            out[m].query_traj = t.qt[o];
+            out[m].entry_traj = t.et[o];
+        } else {  // small merge: the sorted keys carry the ids
+            out[m].query_traj = t.kout[i].qt;
+            out[m].entry_traj = t.kout[i].et;
+        }
         out[m].t_a = t.sta[i];
     }
     if (i == n - 1 || t.start[i + 1]) out[m].t_b = t.runmax[i];
@@ -106,6 +129,15 @@ struct MaxOp {
 };
 struct EqOp {
     __device__ bool operator()(int32_t a, int32_t b) const { return a == b; }
+};
+// (query trajectory, entry trajectory, t_a); equal keys may come in any
+// order, as the merge takes the running maximum of their t_b
+struct TrajLess {
+    __device__ bool operator()(const TrajKey &a, const TrajKey &b) const {
+        if (a.qt != b.qt) return a.qt < b.qt;
+        if (a.et != b.et) return a.et < b.et;
+        return a.ta < b.ta;
+    }
 };
 
 // All rocprim calls of one merge of n items; temp == nullptr only sizes.
@@ -138,6 +170,9 @@ hipError_t traj_rocprim(TrajBufs t, long long n, void *temp, size_t *temp_bytes,
         e = rocprim::inclusive_scan(temp, bytes, t.start, t.mid, (size_t)n,
                                     rocprim::plus<int32_t>(), st);
         break;
+    case 6:  // small merges: one sort of the whole keys
+        e = rocprim::merge_sort(temp, bytes, t.kin, t.kout, (size_t)n, TrajLess(), st);
+        break;
     }
     *temp_bytes = bytes;
     return e;
@@ -148,7 +183,8 @@ hipError_t traj_rocprim(TrajBufs t, long long n, void *temp, size_t *temp_bytes,
 size_t traj_temp_bytes(long long n) {
     size_t most = 0;
     TrajBufs t{};
-    for (int step = 0; step < 6; ++step) {
+    for (int step = 0; step < 7; ++step) {
+        if (step == 6 && n > kTrajOneSortMax) break;
         size_t b = 0;
         if (traj_rocprim(t, n, nullptr, &b, step, 0) != hipSuccess) return 0;
         most = b > most ? b : most;
@@ -163,9 +199,26 @@ hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const i
     if (n <= 0) return hipErrorInvalidValue;  // the caller handles a batch without hits
     const int blk = 256;
     const unsigned g = (unsigned)((n + blk - 1) / blk);
+    const bool one = n <= kTrajOneSortMax;
+    if (one && (!t.kin || !t.kout)) return hipErrorInvalidValue;
+    if (!one) t.kin = t.kout = nullptr;
     hipLaunchKernelGGL(k_traj_gather, dim3(1024), dim3(256), 0, st, sl, ctr, perm, qtraj, ix, t);
     hipError_t e;
     size_t b = temp_bytes;
+    if (one) {
+        if ((e = traj_rocprim(t, n, temp, &b, 6, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_traj_flags_one, dim3(g), dim3(blk), 0, st, t, n);
+        for (int step = 3; step <= 4; ++step) {
+            b = temp_bytes;
+            if ((e = traj_rocprim(t, n, temp, &b, step, st)) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_traj_starts, dim3(g), dim3(blk), 0, st, t, n);
+        b = temp_bytes;
+        if ((e = traj_rocprim(t, n, temp, &b, 5, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_traj_emit, dim3(g), dim3(blk), 0, st, t, (const int32_t *)nullptr, n,
+                           out, total);
+        return hipGetLastError();
+    }
     if ((e = traj_rocprim(t, n, temp, &b, 0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_traj_key, dim3(g), dim3(blk), 0, st, t.et, t.idx_b, t.key_a, n);
     b = temp_bytes;
