@@ -140,6 +140,19 @@ struct TrajLess {
     }
 };
 
+// Merge sort of the small merges: block sort of SortBlock x SortItems keys,
+// then merge passes. Measured on 7,940 hits: 512 keys per block 0.149-0.155
+// ms per merge, 1,024 0.17-0.18, rocprim's default for 32-byte keys 0.195
+// (its block sort alone took 54 us); smaller configurations do not build.
+#ifndef TDS_TRAJ_SORT_BLOCK
+#define TDS_TRAJ_SORT_BLOCK 256
+#endif
+#ifndef TDS_TRAJ_SORT_ITEMS
+#define TDS_TRAJ_SORT_ITEMS 2
+#endif
+using OneSortConfig = rocprim::merge_sort_config<TDS_TRAJ_SORT_BLOCK, TDS_TRAJ_SORT_BLOCK,
+                                                 TDS_TRAJ_SORT_ITEMS>;
+
 // All rocprim calls of one merge of n items; temp == nullptr only sizes.
 hipError_t traj_rocprim(TrajBufs t, long long n, void *temp, size_t *temp_bytes, int step,
                         hipStream_t st) {
@@ -171,7 +184,7 @@ hipError_t traj_rocprim(TrajBufs t, long long n, void *temp, size_t *temp_bytes,
                                     rocprim::plus<int32_t>(), st);
         break;
     case 6:  // small merges: one sort of the whole keys
-        e = rocprim::merge_sort(temp, bytes, t.kin, t.kout, (size_t)n, TrajLess(), st);
+        e = rocprim::merge_sort<OneSortConfig>(temp, bytes, t.kin, t.kout, (size_t)n, TrajLess(), st);
         break;
     }
     *temp_bytes = bytes;
