@@ -900,13 +900,14 @@ int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj
                                hipMemcpyHostToDevice, st));
         qt = q->tr_qtraj.as<int64_t>();
     }
-    // work arrays: the whole keys of a small merge (2 x 32 B), then the
-    // 8-byte ones: qt, et, ta, tb, key_a, key_b, sta, stb, runmax (9 x 8 B),
-    // then idx_a, idx_b, flag, gid, start, mid (6 x 4 B)
+    // work arrays: the whole keys of a small merge (2 x 32 B), the running
+    // maximum's input and output (2 x 16 B), then the 8-byte ones: qt, et,
+    // ta, tb, key_a, key_b, sta (7 x 8 B), then idx_a, idx_b, flag, start,
+    // mid (5 x 4 B)
     const size_t nn = (size_t)n;
     const bool one = n <= kTrajOneSortMax;
     const size_t kbytes = one ? nn * 2 * sizeof(TrajKey) : 0;
-    HIP_TRY(q->tr_work.ensure(kbytes + nn * (9 * 8 + 6 * 4) + 64));
+    HIP_TRY(q->tr_work.ensure(kbytes + nn * (2 * sizeof(SegMax) + 7 * 8 + 5 * 4) + 64));
     char *w = q->tr_work.as<char>();
     auto take8 = [&](void *&dst) { dst = w; w += nn * 8; };
     auto take4 = [&](void *&dst) { dst = w; w += nn * 4; };
@@ -916,10 +917,12 @@ int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj
         t.kout = t.kin + nn;
         w += kbytes;
     }
+    t.seg_in = reinterpret_cast<SegMax *>(w);
+    t.seg_out = t.seg_in + nn;
+    w += nn * 2 * sizeof(SegMax);
     take8((void *&)t.qt); take8((void *&)t.et); take8((void *&)t.ta); take8((void *&)t.tb);
-    take8((void *&)t.key_a); take8((void *&)t.key_b); take8((void *&)t.sta); take8((void *&)t.stb);
-    take8((void *&)t.runmax);
-    take4((void *&)t.idx_a); take4((void *&)t.idx_b); take4((void *&)t.flag); take4((void *&)t.gid);
+    take8((void *&)t.key_a); take8((void *&)t.key_b); take8((void *&)t.sta);
+    take4((void *&)t.idx_a); take4((void *&)t.idx_b); take4((void *&)t.flag);
     take4((void *&)t.start); take4((void *&)t.mid);
     const size_t temp = traj_temp_bytes(n);
     if (temp == 0) return fail(TDS_EDEVICE, "tds_fetch_trajectories: sort sizing failed");

@@ -206,13 +206,20 @@ struct TrajKey {
 // comparison merge sort; larger ones use three stable radix sorts.
 constexpr long long kTrajOneSortMax = 1LL << 16;
 
+// t_b with a pair-start flag: the element of the segmented running maximum.
+struct SegMax {
+    double v;
+    int32_t f, pad;
+};
+
 struct TrajBufs {
     int64_t *qt, *et;                  // trajectory ids, hit order
     double *ta, *tb;                   // interval, hit order
     unsigned long long *key_a, *key_b; // radix-sort keys
     int32_t *idx_a, *idx_b;            // permutations
-    int32_t *flag, *gid, *start, *mid; // sorted order: pair start, pair id, run start, record no.
-    double *sta, *stb, *runmax;        // sorted order: interval, running maximum of t_b
+    int32_t *flag, *start, *mid;       // sorted order: pair start, run start, record no.
+    double *sta;                       // sorted order: t_a
+    SegMax *seg_in, *seg_out;          // sorted order: (t_b, pair start), running maximum of t_b
     TrajKey *kin, *kout;               // small merges: hit order, sorted order
 };
 

@@ -8,7 +8,8 @@
 // trajectory, t_a) with three stable radix sorts (least significant key
 // first; merges of up to kTrajOneSortMax hits instead sort whole 32-byte
 // keys once with a comparison merge sort, a third of the launches), then
-// one segmented running maximum of t_b marks where a new
+// one segmented running maximum of t_b (a single scan whose operator
+// carries the pair-start flag) marks where a new
 // maximal interval starts (its t_a lies after every earlier t_b of the pair;
 // closed intervals that touch merge), and a scan of those marks numbers the
 // output records.
@@ -75,7 +76,7 @@ __global__ void k_traj_flags(TrajBufs t, const int32_t *__restrict__ idx, long l
     }
     t.flag[i] = start ? 1 : 0;
     t.sta[i] = t.ta[o];
-    t.stb[i] = t.tb[o];
+    t.seg_in[i] = SegMax{t.tb[o], start ? 1 : 0, 0};
 }
 
 // The same from the sorted whole keys of a small merge.
@@ -90,7 +91,7 @@ __global__ void k_traj_flags_one(TrajBufs t, long long n) {
     }
     t.flag[i] = start ? 1 : 0;
     t.sta[i] = k.ta;
-    t.stb[i] = k.tb;
+    t.seg_in[i] = SegMax{k.tb, start ? 1 : 0, 0};
 }
 
 // A maximal interval starts where the pair starts or t_a exceeds the running
@@ -98,7 +99,7 @@ __global__ void k_traj_flags_one(TrajBufs t, long long n) {
 __global__ void k_traj_starts(TrajBufs t, long long n) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const bool start = t.flag[i] || t.sta[i] > t.runmax[i - 1];
+    const bool start = t.flag[i] || t.sta[i] > t.seg_out[i - 1].v;
     t.start[i] = start ? 1 : 0;
 }
 
@@ -120,15 +121,16 @@ __global__ void k_traj_emit(TrajBufs t, const int32_t *__restrict__ idx, long lo
         }
         out[m].t_a = t.sta[i];
     }
-    if (i == n - 1 || t.start[i + 1]) out[m].t_b = t.runmax[i];
+    if (i == n - 1 || t.start[i + 1]) out[m].t_b = t.seg_out[i].v;
     if (i == n - 1) *total = m + 1;
 }
 
-struct MaxOp {
-    __device__ double operator()(double a, double b) const { return a > b ? a : b; }
-};
-struct EqOp {
-    __device__ bool operator()(int32_t a, int32_t b) const { return a == b; }
+// Segmented running maximum as one scan: a pair start resets the maximum
+// (the usual flag-carrying operator, associative).
+struct SegMaxOp {
+    __device__ SegMax operator()(const SegMax &a, const SegMax &b) const {
+        return SegMax{b.f ? b.v : (a.v > b.v ? a.v : b.v), a.f | b.f, 0};
+    }
 };
 // (query trajectory, entry trajectory, t_a); equal keys may come in any
 // order, as the merge takes the running maximum of their t_b
@@ -171,13 +173,11 @@ hipError_t traj_rocprim(TrajBufs t, long long n, void *temp, size_t *temp_bytes,
         e = rocprim::radix_sort_pairs(temp, bytes, t.key_a, t.key_b, t.idx_a, t.idx_b, (size_t)n,
                                       0, 64, st);
         break;
-    case 3:  // pair ids
-        e = rocprim::inclusive_scan(temp, bytes, t.flag, t.gid, (size_t)n, rocprim::plus<int32_t>(),
-                                    st);
+    case 3:  // running maximum of t_b within a pair
+        e = rocprim::inclusive_scan(temp, bytes, t.seg_in, t.seg_out, (size_t)n, SegMaxOp(), st);
         break;
-    case 4:  // running maximum of t_b within a pair
-        e = rocprim::inclusive_scan_by_key(temp, bytes, t.gid, t.stb, t.runmax, (size_t)n, MaxOp(),
-                                           EqOp(), st);
+    case 4:  // (no longer a separate step)
+        bytes = 0;
         break;
     case 5:  // output record numbers
         e = rocprim::inclusive_scan(temp, bytes, t.start, t.mid, (size_t)n,
@@ -221,10 +221,8 @@ hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const i
     if (one) {
         if ((e = traj_rocprim(t, n, temp, &b, 6, st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_traj_flags_one, dim3(g), dim3(blk), 0, st, t, n);
-        for (int step = 3; step <= 4; ++step) {
-            b = temp_bytes;
-            if ((e = traj_rocprim(t, n, temp, &b, step, st)) != hipSuccess) return e;
-        }
+        b = temp_bytes;
+        if ((e = traj_rocprim(t, n, temp, &b, 3, st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_traj_starts, dim3(g), dim3(blk), 0, st, t, n);
         b = temp_bytes;
         if ((e = traj_rocprim(t, n, temp, &b, 5, st)) != hipSuccess) return e;
@@ -242,8 +240,6 @@ hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const i
     hipLaunchKernelGGL(k_traj_flags, dim3(g), dim3(blk), 0, st, t, t.idx_b, n);
     b = temp_bytes;
     if ((e = traj_rocprim(t, n, temp, &b, 3, st)) != hipSuccess) return e;
-    b = temp_bytes;
-    if ((e = traj_rocprim(t, n, temp, &b, 4, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_traj_starts, dim3(g), dim3(blk), 0, st, t, n);
     b = temp_bytes;
     if ((e = traj_rocprim(t, n, temp, &b, 5, st)) != hipSuccess) return e;
