@@ -138,7 +138,7 @@ typedef struct {
     int64_t n_refine;    /* pairs the pair kernel passed to the refine kernel: FP32_REFINE the
                             filter's survivors, FP64 the decided hits */
     int64_t n_hit;
-    int64_t n_tiles;     /* tiles (groups of query segments sharing one candidate range) */
+    int64_t n_tiles;     /* tiles: the batches of query segments the pair kernel walks (TDS_TILE_*) */
     int64_t n_items;     /* work units of the pair kernel (query segment x entry chunk) */
     int32_t retries;
     int32_t grid;        /* pair-kernel workgroups used */
