@@ -11,11 +11,12 @@ Written from the paper:
   an entry is clamp(floor((t_start - t_first) / width), 0, m - 1), t_first is
   the smallest t_start and t_last the largest t_end; a bin starts at its
   smallest member t_start; empty bins are not kept.
-* Sec. 4, the candidate range of a time interval (a, b): the entries of the
-  bins whose temporal extent overlaps (a, b) with positive length. The first
-  such bin is the first whose largest end so far exceeds a (a bin's end may
-  be below an earlier bin's end), the last is the last whose start is below
-  b; the range is contiguous in the sorted order.
+* Sec. 4, the candidate range of a time interval (a, b): over the set of bins
+  whose temporal extent [start, end] overlaps (a, b) with positive length
+  (start < b and end > a), first = the smallest first member index and
+  last = the largest last member index; the candidates are the entries
+  first..last of the sorted order (contiguous, and it may take in entries of
+  bins between them that do not overlap (a, b) themselves).
 * Sec. 4, interactions of a batch: the number of its query segments times
   the number of entries in the candidate range of the batch's temporal
   extent [smallest t_start, largest t_end].
@@ -40,7 +41,7 @@ consumed in order, which performs the same merges without list deletions.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import List, Optional, Tuple
 
 import numpy as np
@@ -52,7 +53,7 @@ class Bins:
     end: np.ndarray     # largest member t_end
     first: np.ndarray   # first member (sorted entry index)
     last: np.ndarray    # last member
-    runmax: Optional[np.ndarray] = None  # largest end so far (filled on first use)
+    memo: dict = field(default_factory=dict)  # (a, b) -> candidate range, filled on use
 
 
 def entry_order(t0) -> np.ndarray:
@@ -87,16 +88,20 @@ def bin_table(t0_sorted, t1_sorted, m: int) -> Bins:
 def candidate_range(bins: Bins, a: float, b: float) -> Optional[Tuple[int, int]]:
     """(first, last) sorted entry indices of the bins overlapping (a, b), or None.
 
-    j1 = first bin whose largest end so far exceeds a; j2 = last bin whose
-    start is below b (both by binary search over non-decreasing arrays).
+    Sec. 4 written out: every bin is tested, the overlapping ones give
+    first = min of their first members and last = max of their last members.
     """
-    if bins.runmax is None:
-        bins.runmax = np.maximum.accumulate(bins.end) if bins.end.size else bins.end
-    j1 = int(np.searchsorted(bins.runmax, a, side="right"))
-    j2 = int(np.searchsorted(bins.start, b, side="left")) - 1
-    if j1 > j2 or j1 >= bins.start.size or j2 < 0:
-        return None
-    return int(bins.first[j1]), int(bins.last[j2])
+    key = (float(a), float(b))
+    memo = bins.memo
+    if key in memo:
+        return memo[key]
+    hit = (bins.start < b) & (bins.end > a)
+    if not hit.any():
+        r = None
+    else:
+        r = (int(bins.first[hit].min()), int(bins.last[hit].max()))
+    memo[key] = r
+    return r
 
 
 def _range_size(r) -> int:

@@ -23,10 +23,12 @@ def _to_dec(x: F) -> Decimal:
 
 
 def exact_pair(qrow, erow, d):
-    """Returns dict(code, min_dist2, ta, tb) with code -1 / 0 / 1 as the oracle.
+    """Returns dict(code, min_dist2, ta, tb, vertex) with code -1 / 0 / 1 as the oracle.
 
     ``min_dist2`` is the exact minimum squared distance over the common span
-    (a Fraction), ``ta``/``tb`` floats for hits.
+    (a Fraction), ``ta``/``tb`` floats for hits, ``vertex`` the time of
+    closest approach clamped to the common span (a float; the start of the
+    span when the distance is constant).
     """
     getcontext().prec = 60
     q = _frac_row(qrow)
@@ -35,7 +37,7 @@ def exact_pair(qrow, erow, d):
     tlo = max(q[3], e[3])
     thi = min(q[7], e[7])
     if not tlo < thi:
-        return dict(code=-1, min_dist2=None, ta=None, tb=None)
+        return dict(code=-1, min_dist2=None, ta=None, tb=None, vertex=None)
 
     def pos(s, t):
         w = (t - s[3]) / (s[7] - s[3])
@@ -58,11 +60,13 @@ def exact_pair(qrow, erow, d):
 
     if a == 0:
         fmin = c
+        tv = F(0)
     else:
         tv = -B / a
         tv = min(max(tv, F(0)), T)
         fmin = min(f(tv), c, f(T))
-    res = dict(code=1 if fmin <= 0 else 0, min_dist2=fmin + dd, ta=None, tb=None)
+    res = dict(code=1 if fmin <= 0 else 0, min_dist2=fmin + dd, ta=None, tb=None,
+               vertex=float(_to_dec(tlo + tv)))
     if res["code"] == 1:
         if a == 0:
             lo, hi = Decimal(0), _to_dec(T)

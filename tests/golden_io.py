@@ -46,3 +46,25 @@ def fig2_greedy():
         if tag == "greedy":
             rows.append((v[0], int(v[1]), [int(x) for x in v[2].split(",")], int(v[3])))
     return rows
+
+
+def fig1_sec4():
+    """Hand-worked ranges and two-segment GreedySetSplit cases on Fig. 1's bins."""
+    ranges, greedy = [], []
+    for tag, v in _rows("fig1_sec4_ranges.txt"):
+        if tag == "range":
+            ranges.append((float(v[0]), float(v[1]), int(v[2]), int(v[3])))
+        elif tag == "greedy":
+            segs = [tuple(float(x) for x in p.split(":")) for p in v[2].split(";")]
+            greedy.append((v[0], int(v[1]), segs, [int(x) for x in v[3].split(",")], int(v[4])))
+    return ranges, greedy
+
+
+def r8_collapse():
+    """Query/entry rows (8 values each) and d of the R8 collapse fixture."""
+    out = []
+    for tag, v in _rows("r8_collapse.txt"):
+        if tag == "pair":
+            x = [float.fromhex(t) for t in v]
+            out.append((x[0:8], x[8:16], x[16]))
+    return out

@@ -253,8 +253,41 @@ def pin_near_threshold(lib):
     return f
 
 
+def pin_r8_collapse(lib):
+    """Pairs whose computed entry time falls after the computed exit time
+    (tests/golden/r8_collapse.txt: a pass that comes within d right at the
+    end of the common span) report the single time of closest approach,
+    clamped to the span: t_a == t_b, inside [tlo, thi], equal to the exact
+    clamped vertex within the endpoint tolerance, and the exact minimum
+    distance is d up to the decision's error bound."""
+    from golden_io import r8_collapse
+    f = []
+    cases = r8_collapse()
+    if len(cases) < 4:
+        return [f"r8 fixture holds {len(cases)} pairs"]
+    for k, (qr, er, d) in enumerate(cases):
+        r = oracle.pair(qr, er, d, lib=lib)
+        x = exact_pair(qr, er, d)
+        tlo, thi = max(qr[3], er[3]), min(qr[7], er[7])
+        if r[0] != 1:
+            f.append(f"r8 pair {k}: code {r[0]}")
+            continue
+        if not (r[1] == r[2]):
+            f.append(f"r8 pair {k}: interval [{r[1]}, {r[2]}] is not one time")
+        if not (tlo <= r[1] <= thi):
+            f.append(f"r8 pair {k}: {r[1]} outside [{tlo}, {thi}]")
+        v = x["vertex"]
+        if not abs(r[1] - v) <= 1e-9 * max(1.0, abs(v)):
+            f.append(f"r8 pair {k}: {r[1]} vs exact clamped vertex {v}")
+        margin = abs(float(x["min_dist2"]) - d * d)
+        if margin > _error_bound2(qr, er, d):
+            f.append(f"r8 pair {k}: not near tangency (margin {margin:.3g})")
+    return f
+
+
 ALL_PINS = [pin_worked_value, pin_closed_form, pin_stationary, pin_symmetry,
-            pin_overlap_count, pin_all_hit, pin_sampling, pin_exact, pin_near_threshold]
+            pin_overlap_count, pin_all_hit, pin_sampling, pin_exact, pin_near_threshold,
+            pin_r8_collapse]
 
 
 def run_all(lib):

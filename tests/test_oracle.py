@@ -89,6 +89,10 @@ MUTANTS = {
     "thi_uses_max": ("double thi = dmin(q->t1, e->t1);", "double thi = dmax(q->t1, e->t1);"),
     "Pe_from_query": ("fma(e->vx, te, e->x0)", "fma(e->vx, te, q->x0)"),
     "dd_is_d": ("double dd = qd[i] * qd[i];", "double dd = qd[i];"),
+    # the tangency collapse of reading R8: no value, and the span's start
+    "collapse_nan": ("        a_ = tlo + tv;\n        b_ = a_;", "        a_ = NAN;\n        b_ = a_;"),
+    "collapse_to_tlo": ("        a_ = tlo + tv;\n        b_ = a_;", "        a_ = tlo;\n        b_ = a_;"),
+    "no_collapse": ("    if (a_ > b_) {", "    if (0) {"),
 }
 
 

@@ -3,20 +3,28 @@
 * Fig. 2 worked by hand (tests/golden/fig2_greedy.txt): the free merge of the
   first two groups costs the 180 interactions the paper states; Min and Max
   batch sizes and totals for several bounds; Periodic totals of Fig. 2;
-* the structure of free merges: a merge adds no interactions exactly when
-  the two candidate ranges are identical, so the first pass gives the
-  maximal runs of identical ranges (checked on random inputs);
+* the structure of free merges: a merge adds no interactions only when the
+  two candidate ranges are identical and their hull adds no bin, so the
+  groups of the first pass lie inside the runs of identical ranges, keep
+  their members' range, and no two neighbours merge for free (checked on
+  random inputs);
 * special cases: Min with bound 1 keeps the first pass; a bound of at least
   |Q| gives one batch; with pairwise different ranges Min is Periodic;
 * invariants of the second pass on random inputs (greedy minimality for Min,
   maximality for Max, contiguous partition in t_start order);
 * planted slips (Min with <=, the literal Max swap, no first pass) each break
-  a Fig. 2 pin.
+  a Fig. 2 pin;
+* candidate ranges and two-segment GreedySetSplit cases worked by hand on
+  Fig. 1's bins (tests/golden/fig1_sec4_ranges.txt): a bin that starts
+  before the interval ends but ends before it starts is not a candidate
+  bin, and two segments with identical ranges merge for free only if their
+  hull adds no bin; the superset range "first bin ending after a .. last bin
+  starting before b" (a planted slip) breaks these pins.
 """
 import numpy as np
 import pytest
 
-from golden_io import fig1, fig2, fig2_greedy
+from golden_io import fig1, fig1_sec4, fig2, fig2_greedy
 from oracle import batching as ob
 
 
@@ -73,18 +81,20 @@ def _random_case(seed, n_e=400, n_q=300, m=37):
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
-def test_free_merges_are_runs_of_identical_ranges(seed):
+def test_free_merges_within_runs_of_identical_ranges(seed):
+    """A free merge needs identical ranges, so each group of the first pass
+    lies inside one maximal run of identical per-segment ranges; a run splits
+    further only where the hull of the group so far reaches a bin that none
+    of its members overlaps (Fig. 1 has such a case)."""
     bins, qa, qb = _random_case(seed)
     one = ob.singletons(bins, qa, qb)
     rng_of = [ob.batch_range(bins, b) for b in one]
-    runs = []
-    for k, r in enumerate(rng_of):
-        if runs and rng_of[k - 1] == r:
-            runs[-1] += 1
-        else:
-            runs.append(1)
+    run_start = [k == 0 or rng_of[k - 1] != rng_of[k] for k in range(len(one))]
     groups = ob.free_merges(bins, one)
-    assert [g.n for g in groups] == runs
+    starts = {g.pos for g in groups}
+    assert all(k in starts for k in range(len(one)) if run_start[k])
+    for g in groups:
+        assert not any(run_start[k] for k in range(g.pos + 1, g.pos + g.n))
     assert len(groups) < len(one)  # the case has runs to merge
     # free merges add no interactions
     assert ob.total_interactions(bins, groups) == ob.total_interactions(bins, one)
@@ -167,3 +177,94 @@ def test_planted_slips_are_caught():
     # no first pass
     slip = second_pass(ob.singletons(bins, qa, qb), lambda c, n: c.n < 1)
     assert [b.n for b in slip] != rows[("min", 1)][0]
+
+
+def _fig1_bins():
+    t0, t1, _, _ = fig1()
+    o = ob.entry_order(t0)
+    return ob.bin_table(t0[o], t1[o], 4)
+
+
+def _pin_fig1_sec4(candidate_range):
+    """Failures of the hand-worked Fig. 1 cases under a candidate-range function."""
+    bins = _fig1_bins()
+    ranges, greedy = fig1_sec4()
+    fails = []
+    for a, b, f, l in ranges:
+        got = candidate_range(bins, a, b)
+        want = None if l < f else (f, l)
+        if got != want:
+            fails.append(f"range ({a}, {b}): {got} != {want}")
+    for variant, bound, segs, sizes, total in greedy:
+        qa = np.array([x[0] for x in segs])
+        qb = np.array([x[1] for x in segs])
+        got = ob.greedy_set_split(_fig1_bins(), qa, qb, bound, variant)
+        if [x.n for x in got] != sizes or ob.total_interactions(_fig1_bins(), got) != total:
+            fails.append(f"greedy {variant} {bound} {segs}: {[x.n for x in got]}")
+    return fails
+
+
+def test_fig1_sec4_ranges_and_merges():
+    assert _pin_fig1_sec4(ob.candidate_range) == []
+
+
+def test_superset_range_slip_is_caught(monkeypatch):
+    """The superset range (first bin whose running maximum end exceeds a ..
+    last bin whose start is below b) takes bins that end before the interval
+    starts; it must break the Fig. 1 pins."""
+    def superset(bins, a, b):
+        runmax = np.maximum.accumulate(bins.end)
+        j1 = int(np.searchsorted(runmax, a, side="right"))
+        j2 = int(np.searchsorted(bins.start, b, side="left")) - 1
+        if j1 > j2 or j1 >= bins.start.size or j2 < 0:
+            return None
+        return int(bins.first[j1]), int(bins.last[j2])
+    monkeypatch.setattr(ob, "candidate_range", superset)
+    assert _pin_fig1_sec4(superset) != []
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_candidate_range_brute_force(seed):
+    """Against a direct scan of the entries: the range is the index hull of
+    every entry in an overlapping bin, and it holds every entry whose span
+    overlaps the interval."""
+    rng = np.random.default_rng(seed)
+    n = 300
+    t0 = np.round(rng.uniform(0, 40, n), 1)
+    t1 = t0 + np.round(rng.exponential(4.0, n), 1) + 0.1
+    o = ob.entry_order(t0)
+    e0, e1 = t0[o], t1[o]
+    m = 23
+    bins = ob.bin_table(e0, e1, m)
+    width = (e1.max() - e0[0]) / m
+    j = np.clip(np.floor((e0 - e0[0]) / width), 0, m - 1).astype(int)
+    for a, b in zip(rng.uniform(-3, 45, 200), rng.uniform(0.05, 5, 200)):
+        b = a + b
+        members = []
+        for k in np.unique(j):
+            mk = np.nonzero(j == k)[0]
+            if e0[mk].min() < b and e1[mk].max() > a:
+                members.extend(mk.tolist())
+        got = ob.candidate_range(bins, a, b)
+        if not members:
+            assert got is None
+            continue
+        assert got == (min(members), max(members))
+        ov = np.nonzero((e0 < b) & (e1 > a))[0]
+        assert ov.size == 0 or (got[0] <= ov.min() and ov.max() <= got[1])
+
+
+def test_free_merge_structure():
+    """After the first pass every group's range equals each member's own range
+    (a free merge keeps the range), and merging two neighbouring groups would
+    add interactions."""
+    for seed in (1, 2, 3):
+        bins, qa, qb = _random_case(seed)
+        one = ob.singletons(bins, qa, qb)
+        groups = ob.free_merges(bins, one)
+        for g in groups:
+            r = ob.batch_range(bins, g)
+            for k in range(g.pos, g.pos + g.n):
+                assert ob.batch_range(bins, one[k]) == r
+        for g, h in zip(groups, groups[1:]):
+            assert ob.num_ints(bins, g.merged(h)) > ob.num_ints(bins, g) + ob.num_ints(bins, h)
