@@ -1,20 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark: segment-pair tests/s of the distance-threshold search on one GPU.
 
-Workload (the at-scale plain configuration): a database of 1,000,000
-segments (2,500 Gaussian random-walk trajectories x 400 unit-time steps,
-start positions U[0,1000]^3, sigma = 1 per axis per unit time) indexed with
-1,000 temporal bins, and 40,000 query segments (100 new trajectories of the
-same generator) searched at d = 1, 5 and 25: one step is one query batch of
-the 120,000 (segment, d) pairs through the whole hot path (query records,
-candidate ranges, sort, tiles, pair kernel, compaction, overflow check,
-translation of the hits into caller indices in device memory).
+Headline workload (the precision form): a database of 5,000,000 segments
+(10,000 trajectories x 500 unit-time steps on circular orbits whose radii
+follow a Plummer density, scale radius 1, with N(0, 1e-4^2) jitter per
+axis) indexed with 500 temporal bins, and 100,000 query segments (200 new
+trajectories of the same generator) searched at d = 0.001 and d = 0.01: one
+step is one query batch of the 200,000 (segment, d) pairs through the whole
+hot path (query records, candidate ranges, sort, tiles, pair kernel,
+compaction, overflow check, translation of the hits into caller indices in
+device memory). Both exact forms are timed from the same index: the binary32
+filter + binary64 refine (headline) and the plain binary64 kernel.
 
 value = N_ovl / T_step, where N_ovl is the number of (query, entry) pairs
 whose time spans overlap with positive length (independent of the
 implementation) and T_step the wall time of one step with inputs already in
-device memory. Both exact forms are timed: the binary32 filter + binary64
-refine (headline) and the plain binary64 kernel.
+device memory.
+
+Extras in the same JSON line: the at-scale plain workload (1M-segment
+Gaussian walk, 40,000 query segments x d in {1, 5, 25}) in both forms and
+under each tiling, host-memory (PCIe-inclusive) steps, trajectory-level
+answers, the batching form (uneven queries, autotuned), the response-time
+model, the serving form (10M-segment index, Poisson arrivals) and the oracle
+timed on the host's cores (all, and one).
 """
 from __future__ import annotations
 
@@ -31,22 +39,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "segment-pair tests/s + p99 query latency; FP32+FP64-refine vs FP64, exact hits"
-D_VALUES = (1.0, 5.0, 25.0)
+D_VALUES = (1.0, 5.0, 25.0)      # the at-scale plain workload
 NUM_BINS = 1000
+HEAD_D = (0.001, 0.01)           # the precision-form workload
+HEAD_WORKLOAD = ("C3 precision form: 5M segments on Plummer-sphere circular orbits (10,000 x 500), "
+                 "100,000 query segments x d in {0.001, 0.01} (200,000 per step), 500 bins")
 
 # MI355X peaks (published figures, and the unit counts behind them): binary32
-# vector 157.3 TFLOP/s counts an FMA as 2, i.e. 78.6e12 single binary32
-# operations/s (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz; a dependent-free loop
-# of the filter's own instruction mix measured 2.2 cycles per wave64 binary32
-# instruction per SIMD); binary64 vector 78.6 TFLOP/s (FMA = 2).
+# vector 157.3 TFLOP/s counts an FMA as 2 flops, i.e. 78.6e12 binary32 VALU
+# operations/s = 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz; binary64 vector
+# 78.6 TFLOP/s (FMA = 2), i.e. 39.3e12 binary64 operations/s.
 FP32_OPS_PEAK = 256 * 4 * 32 * 2.4e9
 FP64_PEAK = 78.6e12
-# Algorithmic work per temporally overlapping pair:
-FP64_FLOPS_PER_PAIR = 49          # binary64 decision, FMA = 2
-# binary32 test per candidate pair, max over the axes of |c - C| against the
-# cube's r plus the chunk's largest entry half-width: 3 differences, 3
-# absolute values, 2 maxima (the compare is shared by the 4 pairs of a lane)
-FILTER_OPS_PER_PAIR = 8
+# Algorithmic work per pair:
+FP64_FLOPS_PER_PAIR = 49          # binary64 decision per overlapping pair, FMA = 2
+# binary32 box test per candidate pair: three subtractions, one three-way
+# maximum of their absolute values (absolute value is an operand modifier),
+# one comparison with the threshold
+FILTER_OPS_PER_PAIR = 5
 
 
 def log(*a):
@@ -85,12 +95,12 @@ def overlap_count(db, q) -> int:
     return int((np.searchsorted(t0s, q.t1, side="left") - np.searchsorted(t1s, q.t0, side="right")).sum())
 
 
-def make_workload():
+def make_workload(name="C3"):
     import gen
-    db = gen.make_db("C2")
-    qb = gen.make_queries("C2")
-    q = gen.concat([qb.with_d(d) for d in D_VALUES])
-    return db, q
+    db = gen.make_db(name)
+    qb = gen.make_queries(name)
+    q = gen.concat([qb.with_d(d) for d in (HEAD_D if name == "C3" else D_VALUES)])
+    return db, q, gen.CONFIGS[name]["bins"]
 
 
 def to_device(seg):
@@ -152,13 +162,16 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
                 refine_ms=float(np.median(refine_ms)), opts=opts)
 
 
-def cpu_baseline(db, q, n_ovl_total, target_s=10.0):
-    """The oracle on a bounded sample of query segments (all entries)."""
+def cpu_baseline(db, q, target_s=10.0, nthreads=None, seed=12345, label="all the workload's d"):
+    """The oracle on a bounded sample of query segments (against all entries).
+
+    The sample doubles until one run takes at least target_s / 4; the rate
+    is its overlapping pairs per second of wall time."""
     import oracle
-    nthreads = oracle.default_threads()
-    rng = np.random.default_rng(12345)
+    nthreads = oracle.default_threads() if nthreads is None else int(nthreads)
+    rng = np.random.default_rng(seed)
     order = rng.permutation(len(q))
-    k = 16
+    k = 4
     while True:
         sub = q.subset(np.sort(order[:k]))
         t0 = time.perf_counter()
@@ -168,10 +181,32 @@ def cpu_baseline(db, q, n_ovl_total, target_s=10.0):
             break
         k = min(len(q), int(k * max(2.0, target_s / max(dt, 1e-3))))
     return dict(value=h.n_overlap / dt, unit="pair-tests/s", cores=nthreads, kind="oracle",
-                sample=f"{k} of {len(q)} query segments (random, all three d) against all "
+                sample=f"{k} of {len(q)} query segments (random, {label}) against all "
                        f"{len(db)} entries: {k * len(db):.3g} brute-force pairs, "
-                       f"{h.n_overlap} overlapping, {len(h)} hits, {dt:.2f} s wall",
+                       f"{h.n_overlap} overlapping, {len(h)} hits, {dt:.2f} s wall on {nthreads} threads",
                 seconds=dt)
+
+
+def host_memory_form(ix, q, opts, steps=5, warmup=1):
+    """The step with inputs in host memory and the hits returned to host
+    memory: query upload and result download over PCIe included."""
+    import paper_1405_7461_amd as tds
+    qh = tds.Query(ix)
+    prep = tds.prepare(q, q.d)
+    lat, n_hit = [], 0
+    for i in range(warmup + steps):
+        t0 = time.perf_counter()
+        qh.batch(prep, None, **opts)
+        h = qh.fetch(out="host")
+        t1 = time.perf_counter()
+        if i >= warmup:
+            lat.append(t1 - t0)
+            n_hit = len(h)
+    qh.close()
+    ms = float(np.mean(lat) * 1e3)
+    up = len(q) * 9 * 8
+    return dict(ms_per_step=ms, n_hit=n_hit, bytes_in=up, bytes_out=n_hit * 40,
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3))
 
 
 def trajectory_form(ix, db, dq, q, opts, log_fn=log, steps=10, warmup=2):
@@ -427,6 +462,44 @@ def copy_probe(mib: int):
     log(f"copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches")
 
 
+def roofline_of(name, r, n_ovl):
+    """Roofline of a form's pair kernel from its HIP-event launch time."""
+    if name == "fp32_refine":
+        ach = FILTER_OPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3)
+        return dict(bound="alu", achieved=ach / 1e12, peak=FP32_OPS_PEAK / 1e12, unit="TOP/s",
+                    frac=ach / FP32_OPS_PEAK, kernel="k_pair<fp32_refine>",
+                    per_unit=f"{FILTER_OPS_PER_PAIR} binary32 operations per candidate pair",
+                    units_per_launch=r["n_eval"], launch_ms=r["pair_ms"])
+    ach = FP64_FLOPS_PER_PAIR * n_ovl / (r["pair_ms"] / 1e3)
+    return dict(bound="alu", achieved=ach / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
+                frac=ach / FP64_PEAK, kernel="k_pair<fp64>",
+                per_unit=f"{FP64_FLOPS_PER_PAIR} binary64 flops per overlapping pair",
+                units_per_launch=n_ovl, launch_ms=r["pair_ms"])
+
+
+def time_forms(ix, dq, n_ovl, names, steps, warmup, tag):
+    forms = {
+        "fp32_refine": dict(mode="fp32_refine", tiling="range", block_size=256),
+        "fp64": dict(mode="fp64", tiling="range", block_size=256),
+    }
+    results = {}
+    for name in names:
+        r = run_form(ix, dq, forms[name], steps, warmup, n_ovl)
+        assert r["n_overlap"] == n_ovl, (r["n_overlap"], n_ovl)
+        r["roofline"] = roofline_of(name, r, n_ovl)
+        results[name] = r
+        log(f"{tag} {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} pair-tests/s, pair kernel "
+            f"{r['pair_ms']:.3f} ms ({r['roofline']['frac']:.3f} of its roof), hits {r['n_hit']}, "
+            f"N_eval {r['n_eval']}, refined {r['n_refine']}, retries {r['retries']}")
+    if "fp32_refine" in results and "fp64" in results:
+        assert results["fp32_refine"]["n_hit"] == results["fp64"]["n_hit"]
+    return results, forms
+
+
+def _strip(results):
+    return {k: {kk: vv for kk, vv in v.items() if kk != "opts"} for k, v in results.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,13 +507,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32_refine,fp64")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline workload's forms (for profiler runs)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the at-scale plain workload")
+    ap.add_argument("--no-host", action="store_true", help="skip the host-memory (PCIe) steps")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-trajectories", action="store_true")
     ap.add_argument("--no-model", action="store_true",
                     help="skip the response-time model (calibration and predictions)")
     ap.add_argument("--no-tilings", action="store_true",
-                    help="skip the headline batch under the other tilings")
+                    help="skip the at-scale plain batch under the other tilings")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the forms, run a plain device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters)")
@@ -449,61 +526,34 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library does not "
               "shard a search across GPUs", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_plain = args.no_host = args.no_batching = args.no_serving = True
+        args.no_trajectories = args.no_model = args.no_tilings = args.no_cpu_baseline = True
 
     import torch
     import paper_1405_7461_amd as tds
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    # ------------------------------------------------ headline: precision form
     t0 = time.perf_counter()
-    db, q = make_workload()
+    db, q, m = make_workload("C3")
     n_ovl = overlap_count(db, q)
-    log(f"workload: {len(db)} entries, {len(q)} query segments, N_ovl={n_ovl} "
+    log(f"headline workload: {len(db)} entries, {len(q)} query segments, N_ovl={n_ovl} "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     t0 = time.perf_counter()
-    ix = tds.build_index(db, NUM_BINS)
+    ix = tds.build_index(db, m)
     log(f"index built in {time.perf_counter() - t0:.2f} s: {ix.info()}")
     dq = to_device(q)
     torch.cuda.synchronize()
-
-    forms = {
-        "fp32_refine": dict(mode="fp32_refine", tiling="range", block_size=256),
-        "fp64": dict(mode="fp64", tiling="range", block_size=256),
-    }
-    results = {}
-    for name in args.forms.split(","):
-        r = run_form(ix, dq, forms[name], args.steps, args.warmup, n_ovl)
-        assert r["n_overlap"] == n_ovl, (r["n_overlap"], n_ovl)
-        results[name] = r
-        log(f"{name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} pair-tests/s, pair kernel "
-            f"{r['pair_ms']:.3f} ms, hits {r['n_hit']}, N_eval {r['n_eval']}")
+    results, forms = time_forms(ix, dq, n_ovl, args.forms.split(","), args.steps, args.warmup, "C3")
     if args.copy_probe:
         copy_probe(args.copy_probe)
-    if "fp32_refine" in results and "fp64" in results:
-        assert results["fp32_refine"]["n_hit"] == results["fp64"]["n_hit"]
-
-    for name, r in results.items():  # each form against its own peak
-        if name == "fp32_refine":
-            r["roofline_frac"] = FILTER_OPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3) / FP32_OPS_PEAK
-        else:
-            r["roofline_frac"] = FP64_FLOPS_PER_PAIR * n_ovl / (r["pair_ms"] / 1e3) / FP64_PEAK
     head_name = "fp32_refine" if "fp32_refine" in results else list(results)[0]
     head = results[head_name]
-    if head_name == "fp32_refine":
-        ach = FILTER_OPS_PER_PAIR * head["n_eval"] / (head["pair_ms"] / 1e3)
-        roof = dict(bound="alu", achieved=ach / 1e12, peak=FP32_OPS_PEAK / 1e12, unit="TFLOP/s",
-                    frac=ach / FP32_OPS_PEAK, traffic=measured_traffic("k_pair_fp32_c2_hbm.txt"),
-                    traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                    kernel="k_pair<fp32_refine>", per_unit=f"{FILTER_OPS_PER_PAIR} binary32 ops per candidate pair",
-                    units_per_launch=head["n_eval"], launch_ms=head["pair_ms"])
-    else:
-        ach = FP64_FLOPS_PER_PAIR * n_ovl / (head["pair_ms"] / 1e3)
-        roof = dict(bound="alu", achieved=ach / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
-                    frac=ach / FP64_PEAK, traffic=measured_traffic("k_pair_fp64_c2_hbm.txt"),
-                    traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                    kernel="k_pair<fp64>",
-                    per_unit=f"{FP64_FLOPS_PER_PAIR} binary64 flops per overlapping pair",
-                    units_per_launch=n_ovl, launch_ms=head["pair_ms"])
+    roof = dict(head["roofline"])
+    roof["traffic"] = measured_traffic(f"k_pair_{'fp32' if head_name == 'fp32_refine' else 'fp64'}_c3_hbm.txt")
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -517,25 +567,50 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if head_name == "fp32_refine" else "f64",
         "data": "synthetic",
-        "config": {"workload": "C2 plain at scale: 1M-segment Gaussian random walk (2,500 x 400), "
-                               "40,000 query segments x d in {1,5,25} (120,000 per step), 1,000 bins",
-                   "form": head_name, "n_overlap_per_step": n_ovl, **{k: v for k, v in head["opts"].items()}},
+        "config": {"workload": HEAD_WORKLOAD, "form": head_name, "n_overlap_per_step": n_ovl,
+                   **{k: v for k, v in head["opts"].items()}},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "roofline": roof,
-        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "opts"} for k, v in results.items()},
+        "forms": _strip(results),
     }
-    if not args.no_tilings:
-        line["tilings"] = tiling_comparison(ix, dq, n_ovl)
-    if not args.no_trajectories:
-        line["trajectories"] = trajectory_form(ix, db, dq, q, forms["fp32_refine"])
+    if "fp32_refine" in results and "fp64" in results:
+        line["fp32_refine_vs_fp64"] = results["fp32_refine"]["value"] / results["fp64"]["value"]
+    if not args.no_host:
+        hm = host_memory_form(ix, q, forms[head_name])
+        hm["value"] = n_ovl / (hm["ms_per_step"] / 1e3)
+        line["host_memory"] = hm
+        log(f"C3 {head_name} with host inputs and outputs: {hm['ms_per_step']:.3f} ms/step, "
+            f"{hm['value']:.4g} pair-tests/s")
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(db, q, target_s=10.0, label="both d")
+        cb["one_core"] = cpu_baseline(db, q, target_s=6.0, nthreads=1, seed=54321, label="both d")
+        line["cpu_baseline"] = cb
+        log(f"oracle: {cb['value']:.4g} pair-tests/s on {cb['cores']} threads, "
+            f"{cb['one_core']['value']:.4g} on 1")
+    ix.close()
+    del db, q, dq
+
+    # ------------------------------------------------ at-scale plain workload
+    if not args.no_plain:
+        db2, q2, m2 = make_workload("C2")
+        n2 = overlap_count(db2, q2)
+        ix2 = tds.build_index(db2, m2)
+        dq2 = to_device(q2)
+        r2, forms2 = time_forms(ix2, dq2, n2, ["fp32_refine", "fp64"], args.steps, args.warmup, "C2")
+        line["plain"] = dict(workload="C2 plain at scale: 1M-segment Gaussian random walk (2,500 x 400), "
+                                      "40,000 query segments x d in {1,5,25} (120,000 per step), 1,000 bins",
+                             n_overlap_per_step=n2, forms=_strip(r2))
+        if not args.no_tilings:
+            line["tilings"] = tiling_comparison(ix2, dq2, n2)
+        if not args.no_trajectories:
+            line["trajectories"] = trajectory_form(ix2, db2, dq2, q2, forms2["fp32_refine"])
+        ix2.close()
     if not args.no_batching:
         line["batching"] = batching_form()
     if not args.no_model:
         line["model"] = model_form()
     if not args.no_serving:
         line["serving"] = serving_form()
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(db, q, n_ovl)
     print(json.dumps(line), flush=True)
 
 

@@ -161,3 +161,40 @@ def near_threshold(seed=6, d=1.0, ks=range(4, 53, 4), per_k=4, scale=100.0):
                 rows_q.append([*(e0 + rel0), t0, *(e1 + rel1), t0 + T])
                 tags.append((k, sgn))
     return segments_from_rows(rows_e), segments_from_rows(rows_q).with_d(d), tags
+
+
+def comb_bins(n_gaps=40, per_bin=6, reps=3, seed=7, box=3.0, d=1.5):
+    """Bins of very uneven extent: bin 0 holds one entry spanning the whole
+    time axis [0, n_gaps + 1] (so its extent covers every later bin), every
+    later unit bin k holds short entries inside [k, k + 0.3]. Query segments
+    come in groups of `reps` identical spans (k + 0.5, k + 0.6) in the gaps
+    between the short bins, plus a few random spans. A gap query overlaps
+    bin 0 only, so all gap queries share one candidate range, while the
+    extent of two neighbouring gap groups also overlaps the short bin
+    between them: identical ranges whose merge is not free (Sec. 6, Alg. 4's
+    first pass). Times are multiples of 0.05, exact enough in binary64 for
+    strict comparisons to be unambiguous."""
+    rng = _rng(seed)
+    T = float(n_gaps + 1)
+    rows = []
+    p = rng.uniform(0, box, 3)
+    rows.append([*p, 0.0, *(p + rng.uniform(-1, 1, 3)), T])
+    for k in range(1, n_gaps + 1):
+        for _ in range(per_bin):
+            a = k + 0.05 * rng.integers(0, 3)
+            b = a + 0.05 * rng.integers(1, 3)  # inside [k, k + 0.3]
+            p = rng.uniform(0, box, 3)
+            rows.append([*p, a, *(p + rng.uniform(-0.5, 0.5, 3)), b])
+    db = segments_from_rows(np.array(rows))
+    qrows = []
+    for k in range(1, n_gaps):
+        for _ in range(reps):
+            p = rng.uniform(0, box, 3)
+            qrows.append([*p, k + 0.5, *(p + rng.uniform(-0.5, 0.5, 3)), k + 0.6])
+    for _ in range(n_gaps // 2):
+        a = 0.05 * rng.integers(0, int(T / 0.05) - 4)
+        b = a + 0.05 * rng.integers(1, 40)
+        p = rng.uniform(0, box, 3)
+        qrows.append([*p, a, *(p + rng.uniform(-0.5, 0.5, 3)), min(b, T + 0.5)])
+    q = segments_from_rows(np.array(qrows)[rng.permutation(len(qrows))]).with_d(d)
+    return db, q, n_gaps + 1

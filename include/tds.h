@@ -91,11 +91,11 @@ typedef struct {
 #define TDS_TILE_PERIODIC 0
 #define TDS_TILE_RANGE 1        /* runs of <= batch_size segments with the same candidate bin range */
 /* GreedySetSplit (Sec. 6, Alg. 4) over the query segments with candidates in
- * (t_start, caller index) order: first every run of consecutive segments with
- * the same candidate range becomes one batch (the merges that add no
- * interactions), then a second pass merges each batch with its successor
- * while the batch holds fewer than batch_size segments (Min), or while the
- * merged batch would hold at most batch_size segments (Max). */
+ * (t_start, caller index) order: first neighbours merge while the merge adds
+ * no interactions (same candidate range, and the merged temporal extent
+ * overlaps no further bin), then a second pass merges each batch with its
+ * successor while the batch holds fewer than batch_size segments (Min), or
+ * while the merged batch would hold at most batch_size segments (Max). */
 #define TDS_TILE_GREEDY_MIN 2
 #define TDS_TILE_GREEDY_MAX 3
 
@@ -210,11 +210,13 @@ int tds_plan_bins(const double *t0_sorted, const double *t1_sorted, int64_t n, i
 /*
  * The candidate range of query segments (Sec. 4, host planning helper, no
  * device needed): for each (t0[i], t1[i]) the bins whose temporal extent
- * overlaps it with positive length, i.e. from the first bin whose running
- * maximum end exceeds t0[i] to the last bin whose start is below t1[i];
- * first[i]..last[i] is the union of their index ranges (last < first when
- * empty). bins: the non-empty bins in time order, as tds_plan_bins or
- * tds_index_bins give them.
+ * [start, end] overlaps it with positive length (start < t1[i] and
+ * end > t0[i]); first[i] is the smallest first member and last[i] the
+ * largest last member of those bins (last < first when no bin overlaps).
+ * The device computes the same range for every query segment of a batch.
+ * bins: the non-empty bins in time order, as tds_plan_bins or
+ * tds_index_bins give them. Errors: TDS_EINVAL for negative counts or null
+ * arrays with positive counts.
  */
 int tds_plan_ranges(const tds_bin *bins, int64_t nb, const double *t0, const double *t1,
                     int64_t nq, int64_t *first, int64_t *last);
@@ -254,7 +256,10 @@ typedef struct {
     int32_t q_first; /* first member: position in the member order of tds_query_tiles */
     int32_t n_query; /* member query segments (positions q_first .. q_first + n_query - 1) */
     int32_t e_first; /* candidate range: entries e_first .. e_first + n_entry - 1 of the index,
-                        counted in the index's t_start order (ties in caller order) */
+                        counted in the index's t_start order (ties in caller order). Periodic and
+                        GreedySetSplit tiles take the range of the tile's temporal extent (smallest
+                        t_start to largest t_end of its members, Sec. 4); range tiles the union of
+                        their members' ranges */
     int32_t n_entry;
 } tds_tile_info; /* 16 bytes */
 

@@ -145,6 +145,23 @@ void plan_bins(const double *t0, const double *t1, int64_t n, int32_t m, std::ve
     }
 }
 
+// Max-tree of bin ends for the candidate-range search (bins_of_interval):
+// P leaves (the smallest power of two >= nb), node k < P the larger of
+// nodes 2k and 2k+1; tree[0] is unused.
+int tree_leaves(int64_t nb) {
+    int P = 1;
+    while (P < nb) P <<= 1;
+    return P;
+}
+
+std::vector<double> bin_end_tree(const std::vector<double> &ends) {
+    const int P = tree_leaves((int64_t)ends.size());
+    std::vector<double> t(2 * (size_t)P, -INFINITY);
+    for (size_t j = 0; j < ends.size(); ++j) t[P + j] = ends[j];
+    for (int k = P - 1; k >= 1; --k) t[k] = std::max(t[2 * k], t[2 * k + 1]);
+    return t;
+}
+
 }  // namespace
 
 struct tds_index {
@@ -154,7 +171,7 @@ struct tds_index {
     double t_first = 0, t_last = 0, width = 1;
     std::vector<tds_bin> bins;
     DBuf t0, t1, x0, y0, z0, vx, vy, vz, ecen, orig, traj, t1s;
-    DBuf bstart, bpend, bfirst, blast;
+    DBuf bstart, bpend, bfirst, blast, btree;
     DevIndex dev{};
     int64_t device_bytes = 0;
     int live_queries = 0;
@@ -224,17 +241,19 @@ int tds_plan_ranges(const tds_bin *bins, int64_t nb, const double *t0, const dou
                     int64_t nq, int64_t *first, int64_t *last) {
     if (nb < 0 || nq < 0 || (nb > 0 && !bins) || (nq > 0 && (!t0 || !t1 || !first || !last)))
         return fail(TDS_EINVAL, "tds_plan_ranges: invalid argument");
-    std::vector<double> pend(nb);
-    for (int64_t k = 0; k < nb; ++k) pend[k] = k ? std::max(pend[k - 1], bins[k].end) : bins[k].end;
+    if (nb >= (int64_t)INT32_MAX / 2) return fail(TDS_EINVAL, "tds_plan_ranges: too many bins");
+    std::vector<double> start(nb), pend(nb), end(nb);
+    for (int64_t k = 0; k < nb; ++k) {
+        start[k] = bins[k].start;
+        end[k] = bins[k].end;
+        pend[k] = k ? std::max(pend[k - 1], bins[k].end) : bins[k].end;
+    }
+    const std::vector<double> tree = bin_end_tree(end);
+    const int P = tree_leaves(nb);
     for (int64_t i = 0; i < nq; ++i) {
-        int64_t j1 = std::upper_bound(pend.begin(), pend.end(), t0[i]) - pend.begin();
-        int64_t lo = 0, hi = nb;  // number of bins with start < t1
-        while (lo < hi) {
-            int64_t mid = (lo + hi) / 2;
-            if (bins[mid].start < t1[i]) lo = mid + 1; else hi = mid;
-        }
-        int64_t j2 = lo - 1;
-        if (j1 <= j2) {
+        int j1 = 0, j2 = -1;
+        if (nb > 0 && bins_of_interval(start.data(), pend.data(), tree.data(), P, (int)nb, t0[i], t1[i],
+                                       &j1, &j2)) {
             first[i] = bins[j1].first;
             last[i] = bins[j2].last;
         } else {
@@ -285,14 +304,10 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     std::stable_sort(perm.begin(), perm.end(),
                      [&](int32_t a, int32_t b) { return h[3][a] < h[3][b]; });
     std::vector<double> t0s(n), t1p(n), t1s(n);
-    double ext_max = 0.0, mag_max = 0.0;
     for (int64_t p = 0; p < n; ++p) {
         int32_t i = perm[p];
         t0s[p] = h[3][i];
         t1p[p] = h[7][i];
-        ext_max = std::max(ext_max, std::fabs(h[4][i] - h[0][i]) + std::fabs(h[5][i] - h[1][i]) +
-                                        std::fabs(h[6][i] - h[2][i]));
-        for (int k : {0, 1, 2, 4, 5, 6}) mag_max = std::max(mag_max, std::fabs(h[k][i]));
     }
     t1s = t1p;
     std::sort(t1s.begin(), t1s.end());
@@ -329,14 +344,17 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     IX_TRY(ix->bfirst.ensure(nb1 * 4));
     IX_TRY(ix->blast.ensure(nb1 * 4));
 
-    std::vector<double> bs(nb), bp(nb);
+    std::vector<double> bs(nb), bp(nb), be(nb);
     std::vector<int32_t> bf(nb), bl(nb);
     for (int64_t k = 0; k < nb; ++k) {
         bs[k] = ix->bins[k].start;
+        be[k] = ix->bins[k].end;
         bp[k] = k ? std::max(bp[k - 1], ix->bins[k].end) : ix->bins[k].end;
         bf[k] = (int32_t)ix->bins[k].first;
         bl[k] = (int32_t)ix->bins[k].last;
     }
+    const std::vector<double> bt = bin_end_tree(be);
+    IX_TRY(ix->btree.ensure(bt.size() * 8));
 
     if (n > 0) {
         // Raw arrays to the device (caller order), then gather + derive.
@@ -372,6 +390,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
         IX_TRY(hipMemcpyAsync(ix->bpend.p, bp.data(), nb * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->bfirst.p, bf.data(), nb * 4, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->blast.p, bl.data(), nb * 4, hipMemcpyHostToDevice, st));
+        IX_TRY(hipMemcpyAsync(ix->btree.p, bt.data(), bt.size() * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipStreamSynchronize(st));
         raw.release();
         dperm.release();
@@ -401,15 +420,10 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.bpend = ix->bpend.as<double>();
     d.bfirst = ix->bfirst.as<int32_t>();
     d.blast = ix->blast.as<int32_t>();
-    // Box slack: a binary64 hit implies the exact distance is within
-    // d + 8 sqrt(eps) (d + relative travel) at some common time; 2^-20 keeps
-    // a factor > 10 over that. Positions carry a few ulps of their magnitude;
-    // 2^-40 per unit of magnitude covers it by a wide margin.
-    d.band_rel = std::ldexp(1.0, -20);
-    d.band_abs = std::ldexp(1.0, -40);
-    d.ext_max = ext_max;
-    d.mag_max = mag_max;
-    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 4 + 8 + 8) + nb * 24);
+    d.btree = ix->btree.as<double>();
+    d.bleaf = tree_leaves(nb);
+    d.pad_b = 0;
+    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 4 + 8 + 8) + nb * 24 + (int64_t)bt.size() * 8);
     *out = ix;
     return TDS_OK;
 }
@@ -447,7 +461,7 @@ void tds_index_destroy(tds_index *ix) {
     if (!ix) return;
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
                     &ix->ecen, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
-                    &ix->bfirst, &ix->blast})
+                    &ix->bfirst, &ix->blast, &ix->btree})
         b->release();
     delete ix;
 }
@@ -521,22 +535,34 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
 // chain is marked with `levels` doubling passes, enough for 2^levels - 1
 // batches: with Min every batch but the last holds at least `bound`
 // segments, with Max two neighbouring batches hold more than `bound`.
-static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, bool chain,
-                          GreedyBufs *g) {
+struct GreedySize {
+    int levels;
+    size_t work, jump;  // bytes
+};
+
+static GreedySize greedy_size(int32_t nq, int32_t bound, bool is_max, bool chain) {
     const long long most = is_max ? 2LL * nq / ((long long)bound + 1) + 2 : (long long)nq / bound + 2;
     int levels = 1;
     while (chain && (1LL << levels) <= most) ++levels;
     const size_t n = (size_t)nq, n1 = n + 1;
-    // 8-byte arrays first: kin, tev; then the 4-byte ones, then the flags
+    // 8-byte arrays first: kin, tkey, tev, gmax; then the 4-byte ones, then the flags
     const size_t n16 = (n + 15) & ~(size_t)15;
-    const size_t bytes = n * 8 * 3 + n * 4 * 2 + n1 * 4 * 3 + 2 * 4 + n16 + 64;
-    HIP_TRY(q->gs_work.ensure(bytes));
-    if (chain) HIP_TRY(q->gs_jump.ensure((size_t)levels * n1 * 4));
-    char *w = q->gs_work.as<char>();
+    GreedySize z;
+    z.levels = levels;
+    z.work = n * 8 * 4 + n * 4 * 2 + n1 * 4 * 3 + 2 * 4 + n16 + 64;
+    z.jump = chain ? (size_t)levels * n1 * 4 : 0;
+    return z;
+}
+
+// Lays the greedy work arrays out in `work` (z.work bytes) and `jump`.
+static void carve_greedy(char *w, int32_t *jump, int32_t nq, const GreedySize &z, GreedyBufs *g) {
+    const size_t n = (size_t)nq, n1 = n + 1;
+    const size_t n16 = (n + 15) & ~(size_t)15;
     auto take = [&](size_t b) { char *p = w; w += b; return p; };
     g->kin = (unsigned long long *)take(n * 8);
     g->tkey = (unsigned long long *)take(n * 8);
     g->tev = (long long *)take(n * 8);
+    g->gmax = (double *)take(n * 8);
     g->vout = (int32_t *)take(n * 4);
     g->tidx = (int32_t *)take(n * 4);
     g->gpos = (int32_t *)take(n1 * 4);
@@ -545,9 +571,17 @@ static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, 
     g->cnt = (int32_t *)take(2 * 4);
     w = (char *)(((uintptr_t)w + 15) & ~(uintptr_t)15);
     g->flag = (uint8_t *)take(n16);
-    g->jump = q->gs_jump.as<int32_t>();
+    g->jump = jump;
     g->stride = (int32_t)n1;
-    g->levels = levels;
+    g->levels = z.levels;
+}
+
+static int greedy_buffers(tds_query *q, int32_t nq, int32_t bound, bool is_max, bool chain,
+                          GreedyBufs *g) {
+    const GreedySize z = greedy_size(nq, bound, is_max, chain);
+    HIP_TRY(q->gs_work.ensure(z.work));
+    if (chain) HIP_TRY(q->gs_jump.ensure(z.jump));
+    carve_greedy(q->gs_work.as<char>(), chain ? q->gs_jump.as<int32_t>() : nullptr, nq, z, g);
     return TDS_OK;
 }
 
@@ -607,41 +641,83 @@ static int launch_search(tds_query *q) {
     return TDS_OK;
 }
 
-int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
-                    const tds_query_opts *opts, void *stream) {
-    CallStream call_stream_scope(stream);
-    if (!q || !qs || !opts || (qs->n > 0 && !d)) return fail(TDS_EINVAL, "tds_query_batch: null argument");
-    if (q->pending) return fail(TDS_ESTATE, "tds_query_batch: previous batch not fetched");
+// Checks a batch's arguments and fills in the option defaults (shared by
+// the batch entry points; `who` names the caller).
+static int check_batch(const tds_segments *qs, const double *d, const tds_query_opts *opts,
+                       tds_query_opts *o_out, const char *who) {
+    if (!qs || !opts || (qs->n > 0 && !d)) return fail(TDS_EINVAL, "%s: null argument", who);
     if (qs->n < 0 || qs->n >= (int64_t)INT32_MAX / 2)
-        return fail(TDS_EINVAL, "tds_query_batch: n = %lld out of range", (long long)qs->n);
-    if (qs->mem != TDS_MEM_HOST && qs->mem != TDS_MEM_DEVICE)
-        return fail(TDS_EINVAL, "tds_query_batch: bad mem");
+        return fail(TDS_EINVAL, "%s: n = %lld out of range", who, (long long)qs->n);
+    if (qs->mem != TDS_MEM_HOST && qs->mem != TDS_MEM_DEVICE) return fail(TDS_EINVAL, "%s: bad mem", who);
     tds_query_opts o = *opts;
     if (o.mode != TDS_MODE_FP64 && o.mode != TDS_MODE_FP32_REFINE)
-        return fail(TDS_EINVAL, "tds_query_batch: unknown mode %d", o.mode);
+        return fail(TDS_EINVAL, "%s: unknown mode %d", who, o.mode);
     if (o.tiling != TDS_TILE_PERIODIC && o.tiling != TDS_TILE_RANGE &&
         o.tiling != TDS_TILE_GREEDY_MIN && o.tiling != TDS_TILE_GREEDY_MAX)
-        return fail(TDS_EINVAL, "tds_query_batch: unknown tiling %d", o.tiling);
+        return fail(TDS_EINVAL, "%s: unknown tiling %d", who, o.tiling);
     if (o.batch_size == 0) o.batch_size = 128;
     if (o.batch_size < 1 || o.batch_size > 65536)
-        return fail(TDS_EINVAL, "tds_query_batch: batch_size %d out of 1..65536", o.batch_size);
-    if (o.reserved0 != 0) return fail(TDS_EINVAL, "tds_query_batch: reserved0 must be 0");
+        return fail(TDS_EINVAL, "%s: batch_size %d out of 1..65536", who, o.batch_size);
+    if (o.reserved0 != 0) return fail(TDS_EINVAL, "%s: reserved0 must be 0", who);
     if (o.block_size == 0) o.block_size = 256;
     if (o.block_size != 64 && o.block_size != 128 && o.block_size != 256 && o.block_size != 512 &&
         o.block_size != 1024)
-        return fail(TDS_EINVAL, "tds_query_batch: block_size %d not supported", o.block_size);
+        return fail(TDS_EINVAL, "%s: block_size %d not supported", who, o.block_size);
     if (o.max_retries < 0) o.max_retries = 4;
-    if (o.capacity < 0 || o.grid < 0) return fail(TDS_EINVAL, "tds_query_batch: negative option");
+    if (o.capacity < 0 || o.grid < 0) return fail(TDS_EINVAL, "%s: negative option", who);
     const double *src[8] = {qs->x0, qs->y0, qs->z0, qs->t0, qs->x1, qs->y1, qs->z1, qs->t1};
     const int32_t nq = (int32_t)qs->n;
     if (nq > 0)
         for (int k = 0; k < 8; ++k)
-            if (!src[k]) return fail(TDS_EINVAL, "tds_query_batch: null coordinate array");
+            if (!src[k]) return fail(TDS_EINVAL, "%s: null coordinate array", who);
     if (qs->mem == TDS_MEM_HOST) {  // host inputs are checked here, device ones by the kernel
         for (int32_t i = 0; i < nq; ++i)
             if (!seg_ok(src, i) || !std::isfinite(d[i]) || !(d[i] >= 0.0))
-                return fail(TDS_EINVAL, "tds_query_batch: query segment %d is invalid", i);
+                return fail(TDS_EINVAL, "%s: query segment %d is invalid", who, i);
     }
+    *o_out = o;
+    return TDS_OK;
+}
+
+// The scalar fields of a batch (its buffers are set by the caller).
+static void batch_scalars(DevBatch &b, const tds_query_opts &o, int32_t nq, int nbuckets) {
+    b.nq = nq;
+    b.s = o.batch_size;
+    b.chunk = chunk_for(o.mode, o.block_size);
+    b.tiling = o.tiling;
+    b.nbuckets = nbuckets;
+    b.ntiles_cap = o.tiling == TDS_TILE_PERIODIC ? (nq + o.batch_size - 1) / o.batch_size : nq;
+    b.count_overlap = (o.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0;
+    b.pass_cost = o.mode == TDS_MODE_FP64 ? TDS_PASS_COST64 : TDS_PASS_COST32;
+    b.stage_cost = o.mode == TDS_MODE_FP64 ? TDS_STAGE_COST64 : TDS_STAGE_COST32;
+    b.pad = 0;
+}
+
+// Query preparation and tiling of a batch whose buffers are set (shared by
+// the batch entry points).
+static int enqueue_tiles(DevBatch &b, const GreedyBufs &gb, const tds_index *ix,
+                         const double *const *qin, const double *din, const tds_query_opts &o,
+                         hipStream_t st, hipEvent_t ev_start) {
+    const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
+    const bool sorted = greedy || o.tiling == TDS_TILE_PERIODIC;
+    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st, ev_start));
+    if (sorted && b.nq > 0) HIP_TRY(launch_bucket_sort(b, st));
+    if (o.tiling == TDS_TILE_PERIODIC && b.nq > 0) HIP_TRY(launch_periodic(b, ix->dev, st));
+    if (greedy && b.nq > 0)
+        HIP_TRY(launch_greedy(b, gb, ix->dev, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, st));
+    return TDS_OK;
+}
+
+int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
+                    const tds_query_opts *opts, void *stream) {
+    CallStream call_stream_scope(stream);
+    if (!q) return fail(TDS_EINVAL, "tds_query_batch: null argument");
+    if (q->pending) return fail(TDS_ESTATE, "tds_query_batch: previous batch not fetched");
+    tds_query_opts o;
+    int rc = check_batch(qs, d, opts, &o, "tds_query_batch");
+    if (rc) return rc;
+    const double *src[8] = {qs->x0, qs->y0, qs->z0, qs->t0, qs->x1, qs->y1, qs->z1, qs->t1};
+    const int32_t nq = (int32_t)qs->n;
 
     hipStream_t st = (hipStream_t)stream;
     const tds_index *ix = q->ix;
@@ -649,7 +725,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     q->stream = st;
     q->opts = o;
     q->block = o.block_size;
-    int rc = ensure_capacity(q, std::max<int32_t>(nq, 1), nbuckets);
+    rc = ensure_capacity(q, std::max<int32_t>(nq, 1), nbuckets);
     if (rc) return rc;
     const int kovl = (o.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
     const int grid = pair_grid(o.mode, o.block_size, o.grid, kovl);
@@ -679,15 +755,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     }
 
     DevBatch &b = q->b;
-    b.nq = nq;
-    b.s = o.batch_size;
-    b.chunk = chunk_for(o.mode, o.block_size);
-    b.tiling = o.tiling;
-    b.nbuckets = nbuckets;
-    b.ntiles_cap = o.tiling == TDS_TILE_PERIODIC ? (nq + o.batch_size - 1) / o.batch_size : nq;
-    b.count_overlap = (o.flags & TDS_QF_COUNT_OVERLAP) ? 1 : 0;
-    b.pass_cost = o.mode == TDS_MODE_FP64 ? TDS_PASS_COST64 : TDS_PASS_COST32;
-    b.stage_cost = o.mode == TDS_MODE_FP64 ? TDS_STAGE_COST64 : TDS_STAGE_COST32;
+    batch_scalars(b, o, nq, nbuckets);
     b.rec = q->rec.as<QRec64>();
     b.box = q->box.as<QCube32>();
     b.first = q->first.as<int32_t>();
@@ -723,11 +791,8 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     }
 
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
-    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st, timing ? q->ev[0] : nullptr));
-    if (sorted && nq > 0) HIP_TRY(launch_bucket_sort(b, st));
-    if (o.tiling == TDS_TILE_PERIODIC && nq > 0) HIP_TRY(launch_periodic(b, st));
-    if (greedy && nq > 0)
-        HIP_TRY(launch_greedy(b, gb, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, st));
+    rc = enqueue_tiles(b, gb, ix, qin, din, o, st, timing ? q->ev[0] : nullptr);
+    if (rc) return rc;
     rc = launch_search(q);
     if (rc) return rc;
     q->pending = true;

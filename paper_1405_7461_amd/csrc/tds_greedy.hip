@@ -1,12 +1,16 @@
 // GreedySetSplit tiles (Sec. 6, Alg. 4) built on the device.
 //
 // The algorithm walks the query segments in t_start order twice. Its first
-// pass merges neighbours while the merge adds no interactions; since a
-// batch costs (its segments) x (entries of its candidate range) and a merged
-// range is the hull of the two, a merge is free exactly when the two ranges
-// are identical, so the first pass yields the maximal runs of consecutive
-// segments with identical ranges ("groups"), found from one flag per
-// position.
+// pass merges neighbours while the merge adds no interactions. A batch costs
+// (its segments) x (entries of the candidate range of its temporal extent,
+// Sec. 4), and a merged batch's range holds both ranges, so a merge is free
+// exactly when the two ranges and the range of the merged extent are one and
+// the same. Two conditions mark where a new group ("free-merge group")
+// starts: the segment's range differs from its predecessor's (one flag per
+// position), or, inside a run of identical ranges, the extent of the group
+// so far grows into a bin that none of its members overlaps (a bin lying in
+// a gap between their spans). The second is rare; one wave walks each run of
+// identical ranges to find it.
 //
 // The second pass is sequential in the paper: a batch takes the following
 // groups while it holds fewer than `bound` segments (Min), or while the
@@ -20,7 +24,8 @@
 //
 // Launches: the exact (t_start, caller index) order within each t_start bin
 // (the query preparation's counting sort already orders the bins; this
-// launch also orders Periodic tiling); the run flags; one workgroup for groups, chain and batch starts (in LDS
+// launch also orders Periodic tiling); the run flags; the walk of the runs of
+// identical ranges; one workgroup for groups, chain and batch starts (in LDS
 // when there are fewer than kChainLds groups); the tiles; one workgroup for
 // the unit offsets.
 #include <hip/hip_runtime.h>
@@ -247,7 +252,9 @@ __global__ void k_gs_merge_big(DevBatch b) {
 
 // Run-start flags of the sorted order (one byte per position: 1 where the
 // candidate range differs from the previous position's; positions past the
-// segments with candidates, up to the next multiple of 16, get 0).
+// segments with candidates, up to the next multiple of 16, get 0). k_gs_hull
+// adds 2 where a run of identical ranges splits; every group start is a
+// nonzero byte with one bit set.
 __global__ void k_gs_flags(DevBatch b, GreedyBufs g, int n16) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n16) return;
@@ -256,6 +263,70 @@ __global__ void k_gs_flags(DevBatch b, GreedyBufs g, int n16) {
     if (p < nv)
         flag = (p == 0 || b.first_s[p] != b.first_s[p - 1] || b.last_s[p] != b.last_s[p - 1]) ? 1 : 0;
     g.flag[p] = flag;
+}
+
+// Splits of the runs of identical ranges (the second condition above). Wave w
+// takes positions 64 w .. 64 w + 63 and walks every run that starts among
+// them (flag 1). A run with range R = bins J1..J2 groups segments from its
+// current group start s while every member's t_end stays at or below lim(s),
+// the start of the first bin after J2 that ends after t_start(s): the
+// group's extent (t_start(s), largest t_end) then overlaps no bin beyond J2,
+// and none before J1 either (those end at or before every member's start).
+// The first member past lim(s) starts the next group (flag 2). The walk also
+// records each group's largest t_end (gmax at its start) for the tiles. Only
+// positions inside the wave's own runs are written, and a run's end is found
+// from the ranges, not from flags, so walks of different waves do not meet.
+__device__ __forceinline__ double gs_limit(const DevIndex &ix, int j2, double a) {
+    const int J = bins_first_end_above(ix.btree, ix.bleaf, ix.nb, j2 + 1, a);
+    return J < ix.nb ? ix.bstart[J] : INFINITY;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+__global__ void k_gs_hull(DevBatch b, GreedyBufs g, DevIndex ix) {
+    const int lane = threadIdx.x & 63;
+    const int nv = (int)b.ctr->n_sorted;
+    const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+    for (int c0 = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; c0 < nv; c0 += nwaves * 64) {
+        unsigned long long starts = __ballot(c0 + lane < nv && g.flag[c0 + lane] == 1);
+        while (starts) {
+            const int r0 = c0 + __ffsll((long long)starts) - 1;
+            starts &= starts - 1;
+            const int f = b.first_s[r0], l = b.last_s[r0];
+            const QRec64 q0 = b.rec[b.perm[r0]];
+            int j1 = 0, j2 = -1;
+            (void)bins_of_interval(ix.bstart, ix.bpend, ix.btree, ix.bleaf, ix.nb, q0.t0, q0.t1, &j1, &j2);
+            int s = r0;
+            double lim = gs_limit(ix, j2, q0.t0), mx = q0.t1;
+            for (int p0 = r0 + 1;; p0 += 64) {
+                const int p = p0 + lane;
+                const bool in = p < nv && b.first_s[p] == f && b.last_s[p] == l;
+                const unsigned long long out = __ballot(!in);
+                const int nin = out ? __ffsll((long long)out) - 1 : 64;  // run members p0 .. p0 + nin - 1
+                const bool act = lane < nin;
+                const double t1 = act ? b.rec[b.perm[p]].t1 : -INFINITY;
+                int from = 0;  // lanes below `from` belong to earlier groups
+                for (;;) {
+                    const unsigned long long bad = __ballot(act && lane >= from && t1 > lim);
+                    if (bad == 0ull) break;
+                    const int k = __ffsll((long long)bad) - 1;
+                    mx = fmax(mx, wave_max(lane >= from && lane < k ? t1 : -INFINITY));
+                    if (lane == 0) g.gmax[s] = mx;
+                    s = p0 + k;
+                    if (lane == 0) g.flag[s] = 2;
+                    lim = gs_limit(ix, j2, b.rec[b.perm[s]].t0);
+                    mx = __shfl(t1, k);
+                    from = k + 1;
+                }
+                mx = fmax(mx, wave_max(act && lane >= from ? t1 : -INFINITY));
+                if (nin < 64) break;
+            }
+            if (lane == 0) g.gmax[s] = mx;
+        }
+    }
 }
 
 constexpr int kChainBlock = 1024;
@@ -290,7 +361,7 @@ __device__ long long gs_block_scan(long long v, long long *total) {
 }
 
 __device__ __forceinline__ int flag_count(const uint4 v) {
-    return __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);  // bytes are 0 or 1
+    return __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);  // bytes are 0, 1 or 2
 }
 
 // One workgroup: groups (run starts), next(), the doubling levels, the
@@ -398,33 +469,30 @@ __global__ __launch_bounds__(kChainBlock) void k_gs_chain(DevBatch b, GreedyBufs
 }
 
 // Tiles, one wave at a time (grid-stride over the batches): the members are
-// the groups gb[t] .. gb[t+1]-1, the range is the hull of their (within a
-// group identical) ranges.
+// the groups gb[t] .. gb[t+1]-1, the range is that of the batch's temporal
+// extent (Sec. 4): from the first member's t_start to the largest t_end of
+// its groups.
 constexpr int kTileGrid = 1024;
 
-__global__ void k_gs_tiles(DevBatch b, GreedyBufs g) {
+__global__ void k_gs_tiles(DevBatch b, GreedyBufs g, DevIndex ix) {
     const int lane = threadIdx.x & 63;
     const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
     const int nb = g.cnt[1];
     for (int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); t < nb; t += nwaves) {
         const int g0 = g.gb[t], g1 = g.gb[t + 1];
-        int lo = 0x7fffffff, hi = -1;
-        for (int k = g0 + lane; k < g1; k += 64) {
-            const int p = g.gpos[k];
-            lo = min(lo, b.first_s[p]);
-            hi = max(hi, b.last_s[p]);
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            lo = min(lo, __shfl_xor(lo, off));
-            hi = max(hi, __shfl_xor(hi, off));
-        }
+        double hi_t = -INFINITY;
+        for (int k = g0 + lane; k < g1; k += 64) hi_t = fmax(hi_t, g.gmax[g.gpos[k]]);
+        hi_t = wave_max(hi_t);
         if (lane == 0) {
             const int q0 = g.gpos[g0], nq = g.gpos[g1] - q0;
+            int j1 = 0, j2 = -1;
+            const bool any = bins_of_interval(ix.bstart, ix.bpend, ix.btree, ix.bleaf, ix.nb,
+                                              b.rec[b.perm[q0]].t0, hi_t, &j1, &j2);
             Tile tl;
             tl.q0 = q0;
             tl.nq = nq;
-            tl.e0 = lo;
-            tl.ne = hi - lo + 1;
+            tl.e0 = any ? ix.bfirst[j1] : 0;
+            tl.ne = any ? ix.blast[j2] - ix.bfirst[j1] + 1 : 0;
             tl.nchunk = (tl.ne + b.chunk - 1) / b.chunk;
             tl.echunk = chunk_entries(tl.ne, tl.nchunk);
             tl.pad0 = tl.pad1 = 0;
@@ -482,14 +550,17 @@ hipError_t launch_bucket_sort(DevBatch b, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_greedy(DevBatch b, GreedyBufs g, int bound, int is_max, hipStream_t st) {
+hipError_t launch_greedy(DevBatch b, GreedyBufs g, DevIndex ix, int bound, int is_max,
+                         hipStream_t st) {
     const int nq = b.nq;
     if (nq <= 0) return hipErrorInvalidValue;  // the caller skips an empty batch
     const int blk = 256;
     const int n16 = (nq + 15) & ~15;
     hipLaunchKernelGGL(k_gs_flags, dim3((n16 + blk - 1) / blk), dim3(blk), 0, st, b, g, n16);
+    const int hgrid = (nq + blk - 1) / blk;  // one wave per 64 positions
+    hipLaunchKernelGGL(k_gs_hull, dim3(hgrid < 4096 ? hgrid : 4096), dim3(blk), 0, st, b, g, ix);
     hipLaunchKernelGGL(k_gs_chain, dim3(1), dim3(kChainBlock), 0, st, b, g, bound, is_max);
-    hipLaunchKernelGGL(k_gs_tiles, dim3(kTileGrid), dim3(blk), 0, st, b, g);
+    hipLaunchKernelGGL(k_gs_tiles, dim3(kTileGrid), dim3(blk), 0, st, b, g, ix);
     hipLaunchKernelGGL(k_gs_unit_scan, dim3(1), dim3(kChainBlock), 0, st, b, g);
     return hipGetLastError();
 }

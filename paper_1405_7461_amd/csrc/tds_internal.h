@@ -44,6 +44,89 @@ __host__ __device__ inline int chunk_entries(int ne, int nchunk) {
     return (per + 63) & ~63;
 }
 
+// ------------------------------------------------ bins of an interval (Sec. 4)
+// The candidate bins of an interval (a, b) are those whose temporal extent
+// [start, end] overlaps it with positive length: start < b and end > a. The
+// range runs from the first member of the first such bin to the last member
+// of the last one. Bin starts are non-decreasing (bins are in t_start order)
+// but bin ends are not, so three searches find them: j1 = the first bin whose
+// running maximum end exceeds a (that bin itself ends after a); the last bin
+// starting before b; and from there back to the last bin that also ends
+// after a, found by descending a max-tree of the bin ends.
+//
+// The tree: P = the smallest power of two >= the number of bins; node k in
+// [1, P) holds the largest end of its two children 2k and 2k+1, leaf P + j
+// holds the end of bin j (-inf beyond the last bin).
+
+// Largest j' <= j with end_j' > a, or -1.
+__host__ __device__ inline int bins_last_end_above(const double *tree, int P, int j, double a) {
+    int v = P + j;
+    if (tree[v] > a) return j;
+    while (v > 1) {
+        if ((v & 1) && tree[v - 1] > a) {  // the left sibling holds one: its rightmost
+            v -= 1;
+            while (v < P) {
+                v = 2 * v + 1;
+                if (!(tree[v] > a)) v -= 1;
+            }
+            return v - P;
+        }
+        v >>= 1;
+    }
+    return -1;
+}
+
+// Smallest j' >= j with end_j' > a, or nb.
+__host__ __device__ inline int bins_first_end_above(const double *tree, int P, int nb, int j, double a) {
+    if (j >= nb) return nb;
+    int v = P + j;
+    if (tree[v] > a) return j;
+    while (v > 1) {
+        if (!(v & 1) && tree[v + 1] > a) {  // the right sibling holds one: its leftmost
+            v += 1;
+            while (v < P) {
+                v = 2 * v;
+                if (!(tree[v] > a)) v += 1;
+            }
+            return v - P;
+        }
+        v >>= 1;
+    }
+    return nb;
+}
+
+// First k in [0, n) with a[k] > x (a non-decreasing), n if none.
+__host__ __device__ inline int first_above(const double *a, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+// Number of leading elements < x of a non-decreasing array.
+__host__ __device__ inline int count_below(const double *a, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// The candidate bins j1..j2 of (a, b); false when no bin overlaps it.
+// bstart / bpend: bin starts and running maximum ends (searched, may be
+// copies in LDS); tree: the max-tree of bin ends.
+__host__ __device__ inline bool bins_of_interval(const double *bstart, const double *bpend,
+                                                 const double *tree, int P, int nb, double a,
+                                                 double b, int *j1, int *j2) {
+    *j1 = first_above(bpend, nb, a);
+    const int hi = count_below(bstart, nb, b) - 1;
+    if (*j1 > hi) return false;
+    *j2 = bins_last_end_above(tree, P, hi, a);  // >= j1: bin j1 ends after a
+    return true;
+}
+
 // Segments of one t_start bin sorted in LDS by the bin sort; larger bins are
 // ranked by counting over global memory.
 constexpr int kSortLds = 2048;
@@ -146,11 +229,26 @@ struct DevIndex {
     const double *t1s;    // t_end, sorted independently (overlap counts)
     const double *bstart, *bpend;  // per non-empty bin: min t_start, prefix max of t_end
     const int32_t *bfirst, *blast;
-    double band_rel;      // box slack per unit of (d + query extent + ext_max)
-    double band_abs;      // box slack per unit of coordinate magnitude
-    double ext_max;       // largest |dx|+|dy|+|dz| of an entry segment
-    double mag_max;       // largest |coordinate| of an entry end point
+    const double *btree;  // max-tree of the bin ends (2 * bleaf values)
+    int32_t bleaf;        // leaves of btree: the smallest power of two >= nb
+    int32_t pad_b;
 };
+
+// Error band of the binary32 filter. A binary64 hit of a pair implies that
+// the exact distance is within d + 8 sqrt(eps) (d + ext_q + ext_e) at some
+// common time (ext: |dx| + |dy| + |dz| of a segment; eps = 2^-52, so the
+// factor is 2^-23); kBandRel = 2^-20 is 8 times that. Positions carry a few
+// ulps of their coordinates' magnitude, covered by kBandAbs per unit of
+// magnitude. The band of a pair is split between its two sides: the query
+// cube is widened by kBandRel (d + ext_q) + kBandAbs (1 + d + mag_q + ext_q),
+// each entry's stored half-width by kBandRel ext_e + kBandAbs (mag_e +
+// ext_e), so the band follows the entries of each chunk rather than the
+// largest entry of the database. The binary32 comparison itself rounds by at
+// most 2^-23 (r + H) near the threshold; both sides carry kCmpSlack = 2^-20
+// of their half-width for it.
+constexpr double kBandRel = 0x1p-20;
+constexpr double kBandAbs = 0x1p-40;
+constexpr double kCmpSlack = 0x1p-20;
 
 // Range buckets per first candidate bin: spans of 0, 1, 2 and >= 3 bins.
 constexpr int kSpanClasses = 4;
@@ -239,6 +337,7 @@ struct GreedyBufs {
     int32_t *gb;                     // first group of each batch [nq + 1]
     long long *tev;                  // interactions of each tile [nq]
     int32_t *cnt;                    // [0] groups, [1] batches
+    double *gmax;                    // largest t_end of the group starting at each position [nq]
     int32_t stride;                  // nq + 1
     int32_t levels;                  // doubling levels the jump buffer holds
 };
@@ -274,10 +373,11 @@ size_t traj_temp_bytes(long long n);
 // perm, first_s and last_s in that order (tds_greedy.hip).
 hipError_t launch_bucket_sort(DevBatch b, hipStream_t st);
 // Periodic tiles over the sorted order and their unit and cost offsets.
-hipError_t launch_periodic(DevBatch b, hipStream_t st);
+hipError_t launch_periodic(DevBatch b, DevIndex ix, hipStream_t st);
 // GreedySetSplit tiles (after launch_bucket_sort): builds the runs, the
 // batch chain and the tiles, and scans the work units.
-hipError_t launch_greedy(DevBatch b, GreedyBufs g, int bound, int is_max, hipStream_t st);
+hipError_t launch_greedy(DevBatch b, GreedyBufs g, DevIndex ix, int bound, int is_max,
+                         hipStream_t st);
 hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
                              const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,
                              size_t temp_bytes, tds_traj_hit *out, long long *total,

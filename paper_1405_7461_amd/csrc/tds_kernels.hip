@@ -97,17 +97,21 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
     vx[p] = (a1 - a0) / dt;
     vy[p] = (b1 - b0) / dt;
     vz[p] = (c1 - c0) / dt;
-    float cx, cy, cz, hx, hy, hz;
-    if (dmx(dmx(dmx(fabs(a0), fabs(a1)), dmx(fabs(b0), fabs(b1))), dmx(fabs(c0), fabs(c1))) <=
-        kCubeLimit) {
+    float cx, cy, cz, hx, hy, hz, h;
+    const double mag = dmx(dmx(dmx(fabs(a0), fabs(a1)), dmx(fabs(b0), fabs(b1))), dmx(fabs(c0), fabs(c1)));
+    if (mag <= kCubeLimit) {
         centre_half(dmn(a0, a1), dmx(a0, a1), cx, hx);
         centre_half(dmn(b0, b1), dmx(b0, b1), cy, hy);
         centre_half(dmn(c0, c1), dmx(c0, c1), cz, hz);
+        // the entry's share of the error band and of the comparison's slack
+        const double ext = fabs(a1 - a0) + fabs(b1 - b0) + fabs(c1 - c0);
+        const double hm = (double)fmaxf(fmaxf(hx, hy), hz);
+        h = f32_up(hm + kBandRel * ext + kBandAbs * (mag + ext) + kCmpSlack * hm);
     } else {  // beyond the binary32 test's range: an unbounded box passes every query
         cx = cy = cz = 0.0f;
-        hx = hy = hz = INFINITY;
+        h = INFINITY;
     }
-    ecen[p] = make_float4(cx, cy, cz, fmaxf(fmaxf(hx, hy), hz));
+    ecen[p] = make_float4(cx, cy, cz, h);
     orig[p] = i;
     traj[p] = traj_raw ? traj_raw[i] : (int64_t)i;
 }
@@ -149,15 +153,6 @@ constexpr int kQprepLdsBins = 2048;
 // Groups of lanes with a common bucket that k_qprep ranks with one atomic each.
 constexpr int kRankGroups = 4;
 
-// First index k in [0, nb) with a[k] > x (a non-decreasing), nb if none.
-__device__ __forceinline__ int first_greater(const double *a, int nb, double x) {
-    int lo = 0, hi = nb;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] > x) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
 // Number of leading elements < x of a non-decreasing array.
 __device__ __forceinline__ int64_t count_less(const double *a, int64_t n, double x) {
     int64_t lo = 0, hi = n;
@@ -232,19 +227,15 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         r.pad = 0.0;
         b.rec[i] = r;
 
-        // Box widened by d plus a band covering the binary64 decision's own
-        // rounding (a binary64 hit implies an exact distance below d + band
-        // at some common time) and the rounding of computed positions.
+        // Box widened by d plus the query's share of the error band (the
+        // binary64 decision's own rounding and that of computed positions).
         double ext = fabs(a1 - a0) + fabs(b1 - b0) + fabs(c1 - c0);
         double mag = dmx(dmx(fabs(a0), fabs(a1)), dmx(dmx(fabs(b0), fabs(b1)), dmx(fabs(c0), fabs(c1))));
-        double w = d + ix.band_rel * (d + ext + ix.ext_max) +
-                   ix.band_abs * (1.0 + d + mag + ext + ix.mag_max + ix.ext_max);
-        // The widened box as a cube: centre C and the largest half-width r.
-        // The binary32 test compares max_axis |c - C| with r + H (H the
-        // largest entry half-width of a chunk); its rounding stays below
-        // 2^-22 (r + H) for pairs near the threshold, covered by the
-        // 2^-20 (r + ext_max) slack (entry half-widths are at most
-        // ext_max / 2).
+        double w = d + kBandRel * (d + ext) + kBandAbs * (1.0 + d + mag + ext);
+        // The widened box as a cube: centre C and the largest half-width r,
+        // plus the comparison's slack. The binary32 test compares
+        // max_axis |c - C| with r + H (H the largest entry half-width of a
+        // chunk, band included).
         QCube32 bx;
         if (mag + w <= kCubeLimit) {
             float hx, hy, hz;
@@ -252,25 +243,20 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
             centre_half(dmn(b0, b1) - w, dmx(b0, b1) + w, bx.cy, hy);
             centre_half(dmn(c0, c1) - w, dmx(c0, c1) + w, bx.cz, hz);
             const double r = dmx(dmx((double)hx, (double)hy), (double)hz);
-            bx.r = f32_up(r + 0x1p-20 * (r + ix.ext_max));
+            bx.r = f32_up(r + kCmpSlack * r);
         } else {  // beyond the binary32 test's range: pass every entry
             bx.cx = bx.cy = bx.cz = 0.0f;
             bx.r = INFINITY;
         }
         b.box[i] = bx;
 
-        // Candidate bins: j1 = first bin whose running maximum end exceeds
-        // t0, j2 = last bin whose start is below t1 (spans must overlap with
-        // positive length).
-        int j1, j2;
-        if (in_lds) {
-            j1 = first_greater(s_bins, ix.nb, s0);
-            j2 = (int)count_less(s_bins + ix.nb, ix.nb, s1) - 1;
-        } else {
-            j1 = first_greater(ix.bpend, ix.nb, s0);
-            j2 = (int)count_less(ix.bstart, ix.nb, s1) - 1;
-        }
-        bool any = ok && j1 <= j2;
+        // Candidate bins (Sec. 4): those whose extent overlaps (t0, t1) with
+        // positive length, j1 .. j2 (searches in LDS when the bins fit).
+        int j1 = 0, j2 = -1;
+        const bool found =
+            in_lds ? bins_of_interval(s_bins + ix.nb, s_bins, ix.btree, ix.bleaf, ix.nb, s0, s1, &j1, &j2)
+                   : bins_of_interval(ix.bstart, ix.bpend, ix.btree, ix.bleaf, ix.nb, s0, s1, &j1, &j2);
+        bool any = ok && found;
         b.first[i] = any ? ix.bfirst[j1] : 0;
         b.last[i] = any ? ix.blast[j2] : -1;
 
@@ -556,9 +542,11 @@ __global__ void k_scatter(DevBatch b) {
 }
 
 // Periodic tiles (Sec. 6): one wave per tile of s consecutive query segments
-// in (t_start, caller index) order; the tile's range is the union of its
-// members' ranges.
-__global__ void k_periodic_tiles(DevBatch b) {
+// in (t_start, caller index) order. The tile's candidate range is that of its
+// temporal extent (Sec. 4): from the first member's t_start (the smallest)
+// to the largest t_end of its members; it holds every member's own range and
+// may hold more (a bin between two members' spans that neither overlaps).
+__global__ void k_periodic_tiles(DevBatch b, DevIndex ix) {
     const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (t >= b.ntiles_cap) return;
@@ -566,24 +554,18 @@ __global__ void k_periodic_tiles(DevBatch b) {
     // tiles past the sorted segments (those without candidates are not
     // placed) stay empty
     const int nq = max(0, min(b.s, (int)b.ctr->n_sorted - q0));
-    int lo = 0x7fffffff, hi = -1;
-    for (int k = lane; k < nq; k += 64) {
-        int f = b.first_s[q0 + k], l = b.last_s[q0 + k];
-        if (l >= f) {
-            lo = min(lo, f);
-            hi = max(hi, l);
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, __shfl_xor(lo, off));
-        hi = max(hi, __shfl_xor(hi, off));
-    }
+    double hi_t = -INFINITY;
+    for (int k = lane; k < nq; k += 64) hi_t = dmx(hi_t, b.rec[b.perm[q0 + k]].t1);
+    for (int off = 32; off > 0; off >>= 1) hi_t = dmx(hi_t, __shfl_xor(hi_t, off));
     if (lane == 0) {
+        int j1 = 0, j2 = -1;
+        const bool any = nq > 0 && bins_of_interval(ix.bstart, ix.bpend, ix.btree, ix.bleaf, ix.nb,
+                                                    b.rec[b.perm[q0]].t0, hi_t, &j1, &j2);
         Tile tl;
         tl.q0 = q0;
         tl.nq = nq;
-        tl.e0 = hi >= lo ? lo : 0;
-        tl.ne = hi >= lo ? hi - lo + 1 : 0;
+        tl.e0 = any ? ix.bfirst[j1] : 0;
+        tl.ne = any ? ix.blast[j2] - ix.bfirst[j1] + 1 : 0;
         tl.nchunk = (tl.ne + b.chunk - 1) / b.chunk;
         tl.echunk = chunk_entries(tl.ne, tl.nchunk);
         tl.pad0 = tl.pad1 = 0;
@@ -642,10 +624,10 @@ hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, D
     TDS_LAUNCH_CHECK();
 }
 
-hipError_t launch_periodic(DevBatch b, hipStream_t st) {
+hipError_t launch_periodic(DevBatch b, DevIndex ix, hipStream_t st) {
     const int blk = 256;
     const int waves = b.ntiles_cap;
-    hipLaunchKernelGGL(k_periodic_tiles, dim3((waves * 64 + blk - 1) / blk), dim3(blk), 0, st, b);
+    hipLaunchKernelGGL(k_periodic_tiles, dim3((waves * 64 + blk - 1) / blk), dim3(blk), 0, st, b, ix);
     hipLaunchKernelGGL(k_unit_scan, dim3(1), dim3(kScanBlock), 0, st, b);
     TDS_LAUNCH_CHECK();
 }
@@ -949,9 +931,9 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     return gmin;
                 };
                 // threshold of a query cube against this chunk: r + H. Its
-                // rounding (at most 2^-24 (r + H), H <= ext_max / 2) and that
-                // of the distances lie within the 2^-20 (r + ext_max) slack
-                // the cube's r carries.
+                // rounding and that of the distances (at most 2^-23 (r + H)
+                // near the threshold) lie within the 2^-20 slack that r and
+                // every entry half-width carry.
                 auto thr = [&](const float4 &qc) { return qc.w + H; };
                 auto emit = [&](const float t, const int qs, const float (&gap)[EPT]) {
 #pragma unroll

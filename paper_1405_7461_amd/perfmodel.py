@@ -159,8 +159,8 @@ def workload_terms(index: "api.Index", q, tiling="range", batch_size: int = 128)
 
     range tiling: each segment meets its own candidate range. Periodic:
     consecutive runs of batch_size segments with candidates, in (t_start,
-    caller index) order as the device walks them, meet the hull of their
-    members' ranges.
+    caller index) order as the device walks them, meet the candidate range of
+    their temporal extent (smallest t_start to largest t_end, Sec. 4).
     """
     t0 = np.asarray(q.t0, dtype=np.float64)
     t1 = np.asarray(q.t1, dtype=np.float64)
@@ -172,9 +172,13 @@ def workload_terms(index: "api.Index", q, tiling="range", batch_size: int = 128)
         order = np.argsort(t0, kind="stable")
         order = order[active[order]]
         seg_int = np.zeros_like(size)
-        for s in range(0, order.size, batch_size):
-            grp = order[s:s + batch_size]
-            seg_int[grp] = last[grp].max() - first[grp].min() + 1
+        starts = np.arange(0, order.size, batch_size)
+        if starts.size:
+            lo_t = t0[order[starts]]
+            hi_t = np.maximum.reduceat(t1[order], starts)
+            gf, gl = api.plan_ranges(bins, lo_t, hi_t)
+            for k, s in enumerate(starts):
+                seg_int[order[s:s + batch_size]] = gl[k] - gf[k] + 1
         interactions = float(seg_int.sum())
         n_tiles = -(-order.size // batch_size)
     else:

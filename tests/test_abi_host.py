@@ -164,3 +164,30 @@ def test_index_times_arguments():
     lib = L.lib()
     assert lib.tds_index_times(None, None, None, 0) == L.TDS_EINVAL
     assert b"tds_index_times" in lib.tds_last_error()
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_plan_ranges_equal_oracle(seed):
+    """The library's candidate ranges equal the oracle's Sec. 4 ranges (the
+    bins that overlap the interval, scanned one by one) on entries of very
+    uneven durations, where the last bin starting before an interval's end
+    often ends before its start."""
+    from oracle import batching as ob
+    rng = np.random.default_rng(seed)
+    n = 2000
+    t0 = np.sort(np.round(rng.uniform(0, 100, n), 2))
+    t1 = t0 + np.where(rng.uniform(size=n) < 0.05, rng.exponential(20.0, n), rng.exponential(0.3, n)) + 0.01
+    qa = rng.uniform(-5, 105, 3000)
+    qb = qa + rng.exponential(0.5, 3000) + 1e-3
+    differs = 0
+    for m in (1, 9, 64, 500):
+        bins = tds.plan_bins(t0, t1, m)
+        obins = ob.bin_table(t0, t1, m)
+        f, l = tds.plan_ranges(bins, qa, qb)
+        for i in range(qa.size):
+            r = ob.candidate_range(obins, qa[i], qb[i])
+            assert (f[i], l[i]) == ((0, -1) if r is None else r), (m, i)
+            # the superset end (last bin starting before the interval's end)
+            j2 = np.searchsorted(bins["start"], qb[i], side="left") - 1
+            differs += int(r is not None and bins["last"][j2] != r[1])
+    assert differs > 0  # the case where the two readings part is exercised

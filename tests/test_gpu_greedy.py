@@ -14,7 +14,10 @@ oracle's batches.
   full-size C4, whose short query trajectories at arbitrary times make the
   order within a t_start bin matter;
 * edge cases: no segment with candidates, bound 1, bound >= |Q|, t_start
-  bins holding more query segments than one workgroup sorts in LDS.
+  bins holding more query segments than one workgroup sorts in LDS;
+* the two-segment cases of tests/golden/fig1_sec4_ranges.txt and the comb
+  fixture (bins of very uneven extent, query groups with identical ranges
+  whose merges are not free): tiles identical to the oracle's batches.
 """
 import numpy as np
 import pytest
@@ -24,7 +27,7 @@ from gen import fixtures as fx
 import oracle
 from oracle import batching as ob
 import paper_1405_7461_amd as tds
-from golden_io import fig1, fig2, fig2_greedy
+from golden_io import fig1, fig1_sec4, fig2, fig2_greedy
 from gpu_util import compare, say
 
 pytestmark = pytest.mark.gpu
@@ -184,5 +187,59 @@ def test_edge_cases():
             h, st, tiles, _ = _device(ix, q, v, 1 << 16)
             assert len(tiles) == 1
             compare(h, oracle.search(db, q), db, f"one tile {v}")
+    finally:
+        ix.close()
+
+
+def _time_case(spans, rng):
+    t0, t1, _, _ = fig1()
+    n = t0.size
+    p0 = rng.uniform(0, 5, (n, 3))
+    db = fx.segments_from_rows(np.column_stack([p0, t0, p0 + rng.uniform(-1, 1, (n, 3)), t1]))
+    p = rng.uniform(0, 5, (len(spans), 3))
+    qa = np.array([a for a, _ in spans])
+    qb = np.array([b for _, b in spans])
+    q = fx.segments_from_rows(np.column_stack([p, qa, p + 0.5, qb])).with_d(2.0)
+    return db, q
+
+
+def test_fig1_sec4_greedy_on_device():
+    rng = np.random.default_rng(17)
+    _, greedy = fig1_sec4()
+    for variant, bound, spans, sizes, total in greedy:
+        db, q = _time_case(spans, rng)
+        ix = tds.build_index(db, 4)
+        try:
+            h, st, tiles, members = _device(ix, q, variant, bound)
+        finally:
+            ix.close()
+        label = f"fig1 {variant} {bound} {spans}"
+        assert list(tiles["n_query"]) == sizes, label
+        assert st["n_eval"] == total, label
+        bins, want = _oracle_batches(db, q, 4, bound, variant)
+        _compare_tiles(bins, want, tiles, members, st, label)
+        compare(h, oracle.search(db, q), db, label)
+
+
+def test_comb_bins_tiles_match_oracle():
+    """Identical candidate ranges whose merged extent takes in another bin:
+    the first pass must not merge them (Sec. 4 ranges, Alg. 4)."""
+    db, q, m = fx.comb_bins()
+    o = ob.entry_order(db.t0)
+    bins = ob.bin_table(db.t0[o], db.t1[o], m)
+    one = ob.singletons(bins, q.t0, q.t1)
+    rr = [ob.batch_range(bins, b) for b in one]
+    runs = 1 + sum(rr[k] != rr[k - 1] for k in range(1, len(rr)))
+    assert len(ob.free_merges(bins, one)) > runs  # the fixture hits the case
+    want_hits = oracle.search(db, q)
+    ix = tds.build_index(db, m)
+    try:
+        for variant in ("min", "max", "periodic"):
+            for bound in (1, 2, 3, 7, 64, 1000):
+                h, st, tiles, members = _device(ix, q, variant, bound)
+                _, want = _oracle_batches(db, q, m, bound, variant)
+                _compare_tiles(bins, want, tiles, members, st, f"comb {variant} {bound}")
+                compare(h, want_hits, db, f"comb {variant} {bound}")
+                say(f"comb {variant} {bound}: {len(want)} tiles, n_eval {st['n_eval']}")
     finally:
         ix.close()

@@ -12,7 +12,7 @@ from gen import fixtures as fx
 import oracle
 import paper_1405_7461_amd as tds
 from paper_1405_7461_amd import _lib as L
-from golden_io import fig1
+from golden_io import fig1, fig1_sec4, r8_collapse
 from gpu_util import compare, run, say
 
 pytestmark = pytest.mark.gpu
@@ -68,6 +68,14 @@ def _fixture_cases():
     yield "passing", db, q.with_d(np.array([p["d"] for p in params])), 8
     db, q, _ = fx.stationary_pairs()
     yield "stationary", db, q, 1
+    # pairs whose computed roots cross (reading R8: the interval collapses to
+    # the clamped vertex), each query against every fixture entry
+    pairs = r8_collapse()
+    q = fx.segments_from_rows([p[0] for p in pairs]).with_d(np.array([p[2] for p in pairs]))
+    db = fx.segments_from_rows([p[1] for p in pairs])
+    yield "r8_collapse", db, q, 3
+    db, q, m = fx.comb_bins()
+    yield "comb_bins", db, q, m
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -336,3 +344,56 @@ def test_extreme_magnitudes():
     for mode in MODES:
         got, _, _ = run(db, q, 8, mode=mode)
         compare(got, want, db, f"scale 1e-6 {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_r8_collapse_pairs(mode):
+    """Every fixture pair takes the collapse branch in the oracle; the device
+    reports the same single time, bitwise."""
+    pairs = r8_collapse()
+    q = fx.segments_from_rows([p[0] for p in pairs]).with_d(np.array([p[2] for p in pairs]))
+    db = fx.segments_from_rows([p[1] for p in pairs])
+    want = oracle.search(db, q)
+    diag = {(int(a), int(b)): (x, y) for a, b, x, y in zip(want.q, want.e, want.ta, want.tb)}
+    for k in range(len(pairs)):
+        assert diag[(k, k)][0] == diag[(k, k)][1]  # the collapse: one time
+    got, st, _ = run(db, q, 3, mode=mode, tiling="range")
+    assert compare(got, want, db, f"r8 {mode}")
+
+
+def test_fig1_sec4_ranges_on_device():
+    """The candidate ranges the device computes for the hand-worked intervals
+    of tests/golden/fig1_sec4_ranges.txt (Fig. 1's bins)."""
+    t0, t1, _, _ = fig1()
+    db = fx.time_only(t0, t1)
+    ranges, _ = fig1_sec4()
+    q = fx.segments_from_rows([[0, 0, 0, a, 0, 0, 0, b] for a, b, _, _ in ranges]).with_d(1e9)
+    h, st, (f, l) = run(db, q, 4)
+    for k, (a, b, wf, wl) in enumerate(ranges):
+        if wl < wf:
+            assert l[k] < f[k], (a, b)
+        else:
+            assert (f[k], l[k]) == (wf, wl), (a, b)
+    compare(h, oracle.search(db, q), db, "fig1 sec4 ranges")
+
+
+def test_outlier_band_stays_local():
+    """One entry of huge magnitude and extent widens the binary32 band only
+    for the chunk that holds it: the pairs passed to the refine grow by at
+    most that chunk's share, not by every pair of the batch."""
+    db = gen.make_db("C2", ntraj=300)
+    qb = gen.make_queries("C2", nq=20)
+    q = gen.concat([qb.with_d(x) for x in (1.0, 5.0)])
+    row = np.array([[3e12, -2e12, 1e12, 200.0, -4e12, 5e12, 2e12, 201.0]])
+    out = fx.segments_from_rows(row)
+    out.traj[:] = 999999
+    db2 = gen.concat([db, out])
+    want = oracle.search(db2, q)
+    _, st1, _ = run(db, q, 1000, mode="fp32_refine", tiling="range")
+    got, st2, _ = run(db2, q, 1000, mode="fp32_refine", tiling="range")
+    compare(got, want, db2, "outlier")
+    # query segments whose range holds the outlier's chunk (time step 200)
+    n_step = int(np.sum((q.t0 < 201.0) & (q.t1 > 200.0)))
+    say(f"outlier: refined {st1['n_refine']} -> {st2['n_refine']} ({n_step} query segments at its step)")
+    assert st2["n_refine"] - st1["n_refine"] <= 256 * n_step
+    assert st2["n_refine"] < st1["n_refine"] + 0.05 * st2["n_eval"]
