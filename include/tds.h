@@ -325,6 +325,40 @@ typedef void *(*tds_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*tds_free_fn)(void *ptr, void *stream, void *ctx);
 int tds_set_allocator(tds_alloc_fn alloc, tds_free_fn free_fn, void *ctx);
 
+/*
+ * One search that allocates nothing, for callers that cannot allocate device
+ * memory: code that must not call hipMalloc (tight serving loops, harnesses
+ * that forbid it, work prepared for HIP graph capture). It computes what
+ * tds_query_batch followed by tds_fetch_results(out, cap, TDS_MEM_DEVICE)
+ * computes, with the same kernels, but every per-batch buffer (query records,
+ * ranges, buckets, tiles, counters, result slabs) lives in a fixed device
+ * array of TDS_NOALLOC_SCRATCH_BYTES that the library holds on each device
+ * it runs on until the process ends; no hipMalloc, hipFree, pinned host
+ * memory, event or stream is created.
+ *
+ * q and d must be in device memory (TDS_MEM_DEVICE); out is device memory
+ * for cap records (cap = 0 only counts). The call enqueues the search on
+ * `stream`, waits for it (it reads the hit count), enqueues the translation
+ * of min(cap, n) records into `out` on `stream` and returns: *n_total is the
+ * number of hits, and `out` is complete once `stream` reaches that point.
+ * Options are those of tds_query_batch; capacity and max_retries are
+ * ignored: the result slabs take whatever scratch the batch leaves free.
+ *
+ * Limits and errors: TDS_EINVAL for invalid arguments, host-memory inputs,
+ * an invalid query segment, or a batch whose buffers do not fit the scratch
+ * (the message gives the bytes it needs; about 180 bytes per query segment
+ * plus 2 KiB per pair-kernel wave); TDS_EOVERFLOW when the selected pairs
+ * need more result slabs than the scratch has left (no retry is possible);
+ * TDS_EDEVICE for a failed HIP call. Calls that overlap on one GPU (from
+ * several threads or streams) share its scratch and race; serialize them.
+ * The scratch keeps the last call's contents; every call clears what it
+ * counts before use.
+ */
+#define TDS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int tds_search_noalloc(const tds_index *ix, const tds_segments *q, const double *d,
+                       const tds_query_opts *opts, tds_hit *out, int64_t cap, int64_t *n_total,
+                       void *stream);
+
 const char *tds_last_error(void);
 int tds_abi_version(void);
 

@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     prepare,
     query_batch,
     search,
+    search_noalloc,
     use_torch_allocator,
 )
 from ._lib import TdsError, lib  # noqa: F401

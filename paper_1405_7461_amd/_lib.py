@@ -31,6 +31,7 @@ TDS_QF_TIMING = 1
 TDS_QF_COUNT_OVERLAP = 2
 TDS_QF_KERNEL_OVERLAP = 4
 TDS_QF_TIMING_PAIR = 8
+TDS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _P = C.c_void_p
 
@@ -111,6 +112,8 @@ SIGNATURES = {
     "tds_query_tiles": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64)]),
     "tds_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
+    "tds_search_noalloc": (C.c_int, [_P, C.POINTER(tds_segments), _P, C.POINTER(tds_query_opts), _P,
+                                     C.c_int64, C.POINTER(C.c_int64), _P]),
     "tds_last_error": (C.c_char_p, []),
     "tds_abi_version": (C.c_int, []),
 }

@@ -383,6 +383,26 @@ def search(index: Index, q, d, **opts) -> Hits:
         qh.close()
 
 
+def search_noalloc(index: Index, q, d, out, mode="fp64", tiling="range", batch_size=0, block_size=0,
+                   grid=0, stream=None) -> int:
+    """tds_search_noalloc: one search whose buffers all live in the library's
+    fixed device scratch (no allocation). q: device segments (float64 CUDA
+    tensors), d: thresholds, out: a (cap, 5) int64 CUDA tensor receiving
+    tds_hit records. Returns the number of hits (records beyond cap are
+    counted, not written)."""
+    p = q if isinstance(q, Prepared) else Prepared(q, d)
+    if p.mem != L.TDS_MEM_DEVICE:
+        raise TypeError("search_noalloc takes device segments")
+    o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0, -1, 0,
+                         int(grid), 0)
+    n = C.c_int64()
+    cap = int(out.shape[0]) if out is not None else 0
+    L.check(L.lib().tds_search_noalloc(index.handle, C.byref(p.segments), p.dptr, C.byref(o),
+                                       C.c_void_p(out.data_ptr() if cap else 0), cap, C.byref(n),
+                                       _stream_handle(stream)))
+    return int(n.value)
+
+
 def plan_bins(t0_sorted, t1_sorted, num_bins: int) -> np.ndarray:
     """Host-side bin table of entries already sorted by t_start (no GPU)."""
     t0 = np.ascontiguousarray(t0_sorted, dtype=np.float64)

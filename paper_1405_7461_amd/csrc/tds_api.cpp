@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -202,6 +203,54 @@ struct tds_query {
     tds_stats stats{};
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
+
+// Device scratch of tds_search_noalloc: every per-batch buffer of that entry
+// point (query records, ranges, buckets, tiles, counters, result slabs) is
+// carved from this array, so the call allocates nothing. Each device holds
+// its own copy for the life of the process; its device address is taken once
+// per device with hipGetSymbolAddress (host code must not use the array's
+// name as an address).
+static __device__ __align__(256) unsigned char scratch[TDS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on first use).
+int scratch_ptr(void **out, const char *who) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(TDS_EDEVICE, "%s: hipGetDevice: %s", who, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TDS_EDEVICE, "%s: device %d out of range", who, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TDS_EDEVICE, "%s: hipGetSymbolAddress(scratch): %s", who, hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return TDS_OK;
+}
+
+// Regions laid out one after another from a base address, each aligned to
+// 256 bytes; with a null base it only adds up the size.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    template <class T>
+    T *take(size_t bytes) {
+        used = (used + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += bytes;
+        return p;
+    }
+};
+
+}  // namespace
 
 extern "C" {
 
@@ -642,7 +691,7 @@ static int launch_search(tds_query *q) {
 }
 
 // Checks a batch's arguments and fills in the option defaults (shared by
-// the batch entry points; `who` names the caller).
+// tds_query_batch and tds_search_noalloc; `who` names the caller).
 static int check_batch(const tds_segments *qs, const double *d, const tds_query_opts *opts,
                        tds_query_opts *o_out, const char *who) {
     if (!qs || !opts || (qs->n > 0 && !d)) return fail(TDS_EINVAL, "%s: null argument", who);
@@ -694,7 +743,7 @@ static void batch_scalars(DevBatch &b, const tds_query_opts &o, int32_t nq, int 
 }
 
 // Query preparation and tiling of a batch whose buffers are set (shared by
-// the batch entry points).
+// tds_query_batch and tds_search_noalloc).
 static int enqueue_tiles(DevBatch &b, const GreedyBufs &gb, const tds_index *ix,
                          const double *const *qin, const double *din, const tds_query_opts &o,
                          hipStream_t st, hipEvent_t ev_start) {
@@ -1060,6 +1109,132 @@ int tds_query_ranges(const tds_query *q, int64_t *first, int64_t *last, int64_t 
         first[i] = f[i];
         last[i] = l[i];
     }
+    return TDS_OK;
+}
+
+// The per-batch buffers of one search laid out in `c` (sizes only when its
+// base is null): the same arrays tds_query_batch keeps in its handle, and
+// result slabs for nwaves waves plus `spill` spill slabs.
+static void carve_batch(Carver &c, DevBatch &b, GreedyBufs &gb, Slabs &sl, int32_t nq, int nbuckets,
+                        const tds_query_opts &o, const GreedySize *gz, int32_t nwaves,
+                        long long spill) {
+    const size_t n = (size_t)std::max<int32_t>(nq, 1), n1 = n + 1;
+    b.rec = c.take<QRec64>(n * sizeof(QRec64));
+    b.box = c.take<QCube32>(n * sizeof(QCube32));
+    b.first = c.take<int32_t>(n * 4);
+    b.last = c.take<int32_t>(n * 4);
+    b.first_s = c.take<int32_t>(n * 4);
+    b.last_s = c.take<int32_t>(n * 4);
+    b.key = c.take<int32_t>(n * 4);
+    b.qrank = c.take<int32_t>(n * 4);
+    b.perm = c.take<int32_t>((n + 2) * 4);  // read-ahead slots
+    b.tiles = c.take<Tile>(n1 * sizeof(Tile));
+    b.units = c.take<long long>(n1 * 8);
+    b.unit_off = c.take<long long>(n1 * 8);
+    b.cost_off = c.take<long long>(n1 * 8);
+    b.ctr = c.take<Counters>(sizeof(Counters));
+    b.bcount = c.take<int32_t>((size_t)nbuckets * kBucketSub * 4);
+    b.bq_off = c.take<int32_t>((size_t)nbuckets * kBucketSub * 4);
+    b.bj2 = c.take<int32_t>((size_t)nbuckets * 4);
+    b.skey = b.tkey = nullptr;
+    b.sidx = b.tidx = nullptr;
+    if (gz) {
+        char *w = c.take<char>(gz->work);
+        int32_t *j = gz->jump ? c.take<int32_t>(gz->jump) : nullptr;
+        if (c.base) {
+            carve_greedy(w, j, nq, *gz, &gb);
+            b.skey = gb.kin;
+            b.sidx = gb.vout;
+            b.tkey = gb.tkey;
+            b.tidx = gb.tidx;
+        }
+    }
+    const long long ns = (long long)nwaves + 1 + spill;
+    sl.wave_ovl = c.take<unsigned long long>((size_t)nwaves * 8);
+    sl.cand = c.take<Cand>((size_t)ns * kSlab * sizeof(Cand));
+    sl.hits = c.take<Hit24>((size_t)ns * kSlab * sizeof(Hit24));
+    sl.slab_n = c.take<int32_t>((size_t)ns * 4);
+    sl.slab_h = c.take<int32_t>((size_t)ns * 4);
+    sl.hit_off = c.take<long long>((size_t)(ns + 1) * 8);
+    sl.nwaves = nwaves;
+    sl.pad = 0;
+    sl.nslabs = ns;
+    (void)o;
+}
+
+int tds_search_noalloc(const tds_index *ix, const tds_segments *qs, const double *d,
+                       const tds_query_opts *opts, tds_hit *out, int64_t cap, int64_t *n_total,
+                       void *stream) {
+    const char *who = "tds_search_noalloc";
+    if (!ix || !n_total || cap < 0 || (cap > 0 && !out)) return fail(TDS_EINVAL, "%s: invalid argument", who);
+    *n_total = 0;
+    tds_query_opts o;
+    int rc = check_batch(qs, d, opts, &o, who);
+    if (rc) return rc;
+    if (qs->mem != TDS_MEM_DEVICE)
+        return fail(TDS_EINVAL, "%s: query segments and thresholds must be in device memory", who);
+    const int32_t nq = (int32_t)qs->n;
+    const int nbuckets = nbuckets_for(o.tiling, ix->dev.nb, ix->dev.m);
+    const int kovl = (o.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
+    const int grid = pair_grid(o.mode, o.block_size, o.grid, kovl);
+    if (grid < 1 || (long long)grid * (o.block_size / 64) > INT32_MAX / kSlab)
+        return fail(TDS_EINVAL, "%s: grid %d not supported", who, grid);
+    const int32_t nwaves = grid * (o.block_size / 64);
+    const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
+    const bool sorted = greedy || o.tiling == TDS_TILE_PERIODIC;
+    GreedySize gz{};
+    if (sorted && nq > 0) gz = greedy_size(nq, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, greedy);
+
+    // Layout: the fixed part with one spill slab, then as many spill slabs as fit.
+    DevBatch b{};
+    GreedyBufs gb{};
+    Slabs sl{};
+    Carver sizing{nullptr};
+    carve_batch(sizing, b, gb, sl, nq, nbuckets, o, sorted && nq > 0 ? &gz : nullptr, nwaves, 1);
+    const size_t fixed = sizing.used;
+    if (fixed > (size_t)TDS_NOALLOC_SCRATCH_BYTES)
+        return fail(TDS_EINVAL,
+                    "%s: a batch of %d query segments with %d workgroups of %d threads needs %zu bytes "
+                    "of scratch, more than the %zu available (TDS_NOALLOC_SCRATCH_BYTES); use "
+                    "tds_query_batch or a smaller batch",
+                    who, nq, grid, o.block_size, fixed, (size_t)TDS_NOALLOC_SCRATCH_BYTES);
+    // each further spill slab: its candidates, hits, two counts and an offset;
+    // 6 x 256 bytes cover the alignment of the regions that grow
+    const size_t per_slab = kSlab * (sizeof(Cand) + sizeof(Hit24)) + 4 + 4 + 8;
+    const size_t room = (size_t)TDS_NOALLOC_SCRATCH_BYTES - fixed;
+    const long long spill = 1 + (room > 6 * 256 ? (long long)((room - 6 * 256) / per_slab) : 0);
+    void *base = nullptr;
+    rc = scratch_ptr(&base, who);
+    if (rc) return rc;
+    Carver c{static_cast<char *>(base)};
+    carve_batch(c, b, gb, sl, nq, nbuckets, o, sorted && nq > 0 ? &gz : nullptr, nwaves,
+                std::max<long long>(spill, 1));
+    if (c.used > (size_t)TDS_NOALLOC_SCRATCH_BYTES)
+        return fail(TDS_EINVAL, "%s: scratch layout of %zu bytes exceeds the maximum", who, c.used);
+    batch_scalars(b, o, nq, nbuckets);
+
+    hipStream_t st = (hipStream_t)stream;
+    const double *qin[8] = {qs->x0, qs->y0, qs->z0, qs->t0, qs->x1, qs->y1, qs->z1, qs->t1};
+    rc = enqueue_tiles(b, gb, ix, qin, d, o, st, nullptr);
+    if (rc) return rc;
+    if (nq > 0) {
+        HIP_TRY(launch_pair(b, ix->dev, o.mode, o.block_size, o.grid, kovl, sl, st));
+        HIP_TRY(launch_refine(b, ix->dev, sl, kovl, st, nullptr, nullptr));
+    }
+    Counters ctr{};
+    HIP_TRY(hipMemcpyAsync(&ctr, b.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctr.err)
+        return fail(TDS_EINVAL, "%s: the batch holds an invalid query segment (non-finite value, "
+                                "t_end <= t_start, or d < 0)", who);
+    if (ctr.spill > (unsigned long long)(sl.nslabs - sl.nwaves))
+        return fail(TDS_EOVERFLOW,
+                    "%s: the selections needed %llu spill slabs of %d records beyond the wave slabs; "
+                    "the scratch holds %lld",
+                    who, ctr.spill, kSlab, (long long)(sl.nslabs - sl.nwaves));
+    *n_total = (int64_t)ctr.hits;
+    const int64_t m = std::min<int64_t>(cap, (int64_t)ctr.hits);
+    if (m > 0) HIP_TRY(launch_translate(sl, b.ctr, m, b.perm, ix->dev, out, st));
     return TDS_OK;
 }
 
