@@ -50,7 +50,7 @@ extern "C" {
 #define TDS_EINVAL (-1)    /* null pointer, n < 0, t_end <= t_start, non-finite value, d < 0, bad option */
 #define TDS_ENOMEM (-2)    /* device or host allocation failed */
 #define TDS_EDEVICE (-3)   /* a HIP call failed (message names it) */
-#define TDS_EOVERFLOW (-4) /* more hits than the result buffer after all retries */
+#define TDS_EOVERFLOW (-4) /* more selected pairs than the result slabs hold after all retries */
 #define TDS_ESTATE (-5)    /* call out of order (e.g. fetch before a query) */
 
 /* Where the arrays of a tds_segments live. */
@@ -114,7 +114,9 @@ typedef struct {
     int32_t block_size;  /* pair-kernel threads per workgroup: 64, 128, 256, 512 or 1024; 0 = 256 */
     int32_t reserved0;   /* 0 */
     int32_t max_retries; /* result-buffer regrowths allowed; < 0 = 4 */
-    int64_t capacity;    /* initial result capacity (hits); 0 = library default */
+    int64_t capacity;    /* initial result capacity, counted in pair-kernel selections beyond the
+                            per-wave result slabs: FP64 the decided hits, FP32_REFINE the binary32
+                            filter's survivors (hits and near-threshold pairs); 0 = 1,048,576 */
     int32_t grid;        /* pair-kernel workgroups; 0 = as many as are resident at once */
     int32_t flags;       /* TDS_QF_* */
 } tds_query_opts;
@@ -228,10 +230,23 @@ void tds_query_destroy(tds_query *qh);
 
 /*
  * Start the search of query segments q (with per-segment thresholds d[i] >= 0,
- * n values, in the same memory space as q) against the index, on `stream`.
+ * n values, in the same memory space as q) against the index, on `stream`:
+ * the distance threshold query of Sec. 3 for one set of query segments. Each
+ * query segment gets its candidate range from the bins (Sec. 4); the segments
+ * are grouped into tiles (opts->tiling: range buckets, Periodic or
+ * GreedySetSplit, Sec. 6); every candidate pair goes through the temporal
+ * intersection and the degree-two polynomial of the squared distance
+ * (Sec. 5, Alg. 1), decided in binary64 (TDS_MODE_FP64) or first screened by
+ * a conservative binary32 test whose survivors are decided in binary64
+ * (TDS_MODE_FP32_REFINE; the hit set is the same); hits are compacted into
+ * the result slabs (Alg. 1: appended to the result set).
  * Returns once the work is enqueued; inputs in device memory must stay valid
  * until tds_fetch_results returns. Inputs in host memory are copied first.
- * Invalid device-resident segments are reported by tds_fetch_results.
+ * Errors: TDS_EINVAL for null pointers, n out of range, an unknown mode,
+ * tiling or block size, or (host inputs) an invalid segment or threshold;
+ * TDS_ESTATE when the previous batch of the handle was not fetched;
+ * TDS_ENOMEM / TDS_EDEVICE for failed device calls. Invalid device-resident
+ * segments are reported by tds_fetch_results.
  */
 int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
                     const tds_query_opts *opts, void *stream);

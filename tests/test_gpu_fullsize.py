@@ -46,8 +46,11 @@ def _check_hits_one_by_one(db, q, h, label, limit=20000):
         assert int(h.traj[k]) == int(db.traj[ei]), f"{label}: trajectory id of entry {ei}"
 
 
-def _check_sample(db, q, h, nsample, seed, label):
-    sel = np.sort(np.random.default_rng(seed).choice(len(q), min(nsample, len(q)), replace=False))
+def _check_sample(db, q, h, nsample, seed, label, extra=None):
+    sel = np.random.default_rng(seed).choice(len(q), min(nsample, len(q)), replace=False)
+    if extra is not None:
+        sel = np.union1d(sel, extra)
+    sel = np.sort(sel)
     want = oracle.search(db, q.subset(sel))
     # device hits of the sampled segments, renumbered to sample positions
     pos = np.full(len(q), -1, np.int64)
@@ -72,7 +75,18 @@ def _search(ix, q, mode):
     return h, st
 
 
-def _full_case(db, q, m, nsample, label):
+def _hit_segments(q, h, per_d, limit, seed):
+    """Segments that hold device hits, with their copies at the other
+    thresholds (the batch repeats the query set once per d, per_d segments
+    each): at most `limit` of them, seeded."""
+    base = np.unique(np.asarray(h.query) % per_d)
+    if len(base) > limit:
+        base = np.sort(np.random.default_rng(seed).choice(base, limit, replace=False))
+    ncopies = len(q) // per_d
+    return np.concatenate([base + k * per_d for k in range(ncopies)])
+
+
+def _full_case(db, q, m, nsample, label, hit_sample=0, per_d=None):
     n_ovl = _overlap_closed_form(db, q)
     ix = tds.build_index(db, m)
     try:
@@ -87,8 +101,11 @@ def _full_case(db, q, m, nsample, label):
     assert np.array_equal(h32.query, h64.query) and np.array_equal(h32.entry, h64.entry), label
     assert np.array_equal(h32.ta, h64.ta) and np.array_equal(h32.tb, h64.tb), label
     _check_hits_one_by_one(db, q, h64, label)
-    ns = _check_sample(db, q, h64, nsample, 99, label)
-    say(f"{label}: all hits confirmed pair by pair; sample of {nsample} segments matched ({ns} hits)")
+    extra = _hit_segments(q, h64, per_d, hit_sample, 98) if hit_sample else None
+    ns = _check_sample(db, q, h64, nsample, 99, label, extra)
+    nx = 0 if extra is None else len(extra)
+    say(f"{label}: all hits confirmed pair by pair; sample of {nsample} random segments and {nx} "
+        f"segments with hits (every d) matched the oracle ({ns} hits)")
     return h64
 
 
@@ -104,7 +121,11 @@ def test_c3_full_size():
     db = gen.make_db("C3")
     qb = gen.make_queries("C3")
     q = gen.concat([qb.with_d(d) for d in (0.001, 0.01)])
-    _full_case(db, q, gen.CONFIGS["C3"]["bins"], 48, "C3 full")
+    # 512 random (segment, d) pairs and every d of up to 192 segments with
+    # hits: hits are rare at these thresholds, so random segments alone
+    # would mostly check empty answers
+    h = _full_case(db, q, gen.CONFIGS["C3"]["bins"], 512, "C3 full", hit_sample=192, per_d=len(qb))
+    assert len(h) > 0
 
 
 def test_c4_full_size():
