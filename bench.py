@@ -388,65 +388,95 @@ def model_form(log_fn=log, steps=8, warmup=2):
     return out
 
 
-def serving_form(log_fn=log, n_requests=400, rates=(0.5, 0.8, 0.95)):
-    """C5: 10M-segment resident index, Poisson request arrivals at 3 rates."""
+def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4):
+    """C5: 10M-segment resident index; requests served by the library's
+    native scheduler (tds_server_*: admission by estimated result bytes,
+    continuous batching over `streams` HIP streams, per-request split in
+    native code). Open-loop load: each request is submitted with its arrival
+    time (all at 0 for the saturation run, Poisson at 3 fractions of the
+    saturation rate otherwise); latency = done - arrival on the server's
+    clock. The request arrays are generated once and reused by every run."""
     import gen
     import paper_1405_7461_amd as tds
-    from paper_1405_7461_amd.serving import Request, Server, poisson_arrivals
+    from paper_1405_7461_amd.serving import poisson_arrivals
     t0 = time.perf_counter()
     db = gen.make_db("C5")
     ix = tds.build_index(db, gen.CONFIGS["C5"]["bins"])
-    t1s = np.sort(db.t1)
-    t0s = np.sort(db.t0)
+    t1s, t0s = np.sort(db.t1), np.sort(db.t0)
+    del db
     build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    reqs = [gen.make_queries("C5", request=i) for i in range(n_requests)]
+    n_ovl = np.array([int((np.searchsorted(t0s, q.t1, side="left")
+                           - np.searchsorted(t1s, q.t0, side="right")).sum()) for q in reqs])
+    n_seg = np.array([len(q) for q in reqs])
+    gen_s = time.perf_counter() - t0
+    log_fn(f"serving: index {build_s:.1f} s, {n_requests} requests ({n_seg.sum()} segments, "
+           f"{n_ovl.sum():.4g} overlapping pairs) generated in {gen_s:.1f} s")
 
-    def make(n, arrivals):
-        reqs = []
-        for i in range(n):
-            q = gen.make_queries("C5", request=i)
-            r = Request(rid=i, seg=q, d=q.d.copy(), arrival=float(arrivals[i]))
-            r.n_overlap = int((np.searchsorted(t0s, q.t1, side="left") - np.searchsorted(t1s, q.t0, side="right")).sum())
-            reqs.append(r)
-        return reqs
+    def serve(arrivals, warm=False):
+        srv = tds.NativeServer(ix, streams=streams, max_batch_segments=65536,
+                               mode="fp32_refine", tiling="range")
+        if warm:  # first batches of a fresh server: untimed
+            ids = [srv.submit(q, q.d, 0.0) for q in reqs[:256]]
+            for i in ids:
+                srv.wait(i)
+        # every request is submitted before the first one arrives, so the
+        # Python submission loop never paces the load
+        base = srv.now() + 1.5
+        ids = [srv.submit(q, q.d, base + float(a)) for q, a in zip(reqs, arrivals)]
+        assert srv.now() < base, "submission took longer than the lead time"
+        infos = [srv.wait(i) for i in ids]
+        st = srv.stats()
+        srv.close()
+        assert all(x["status"] == 0 for x in infos)
+        arr = np.array([x["arrival"] for x in infos])
+        done = np.array([x["done"] for x in infos])
+        adm = np.array([x["admit"] for x in infos])
+        lat = done - arr
+        wall = done.max() - arr.min()
+        return dict(wall_s=wall, p50_ms=float(np.percentile(lat, 50) * 1e3),
+                    p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                    p99_wait_ms=float(np.percentile(adm - arr, 99) * 1e3),
+                    p99_service_ms=float(np.percentile(done - adm, 99) * 1e3),
+                    batches=int(st["batches"]), retries=int(st["retries"]),
+                    mean_batch_requests=float(np.mean([x["n_batch_requests"] for x in infos])),
+                    hits=int(sum(x["n_hit"] for x in infos)), busy_s=float(st["busy_s"]),
+                    device_bytes=int(st["device_bytes"]))
 
-    opts = dict(mode="fp32_refine", tiling="range")
-    # a few of the largest requests grow every executor's buffers before timing
-    warm = sorted(make(64, np.zeros(64)), key=lambda r: -r.n)[:4]
-    # saturation: every request waiting at t = 0
-    reqs = make(n_requests, np.zeros(n_requests))
-    srv = Server(ix, pool_bytes=256e6, streams=2, opts=opts)
-    srv.warmup(warm, reserve_segments=1 << 16)
-    sat = srv.run(reqs)
-    srv.close()
+    sat = serve(np.zeros(n_requests), warm=True)
     sat_rate = n_requests / sat["wall_s"]
-    sat_pairs = sum(r.n_overlap for r in reqs) / sat["wall_s"]
-    # one untimed run at the lowest rate: the first paced run of a process
-    # showed a one-time stall of a few ms on its first batches (not seen in
-    # later runs), which the warm-up of the query handles alone did not remove
-    srv = Server(ix, pool_bytes=256e6, streams=2, opts=opts)
-    srv.warmup(warm, reserve_segments=1 << 16)
-    srv.run(make(n_requests // 2, poisson_arrivals(n_requests // 2, rates[0] * sat_rate, seed=14057461 + 499)))
-    srv.close()
+    log_fn(f"serving saturation: {sat_rate:.0f} req/s, {n_ovl.sum() / sat['wall_s']:.4g} pair-tests/s, "
+           f"{sat['batches']} batches, p50 {sat['p50_ms']:.2f} ms")
     runs = []
     for k, f in enumerate(rates):
         arr = poisson_arrivals(n_requests, f * sat_rate, seed=14057461 + 500 + k)
-        reqs = make(n_requests, arr)
-        srv = Server(ix, pool_bytes=256e6, streams=2, opts=opts)
-        srv.warmup(warm, reserve_segments=1 << 16)
-        st = srv.run(reqs)
-        srv.close()
+        st = serve(arr)
         runs.append(dict(rate_frac=f, rate_req_s=f * sat_rate, p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
                          p99_wait_ms=st["p99_wait_ms"], p99_service_ms=st["p99_service_ms"],
-                         retries=st["retries"],
-                         pair_tests_s=sum(r.n_overlap for r in reqs) / st["wall_s"],
-                         mean_batch_requests=st["mean_batch_requests"], batches=st["n_batches"]))
+                         retries=st["retries"], pair_tests_s=float(n_ovl.sum() / st["wall_s"]),
+                         mean_batch_requests=st["mean_batch_requests"], batches=st["batches"]))
         log_fn(f"serving at {f:.2f} x saturation ({f * sat_rate:.0f} req/s): p50 {st['p50_ms']:.3f} ms, "
                f"p99 {st['p99_ms']:.3f} ms, {runs[-1]['pair_tests_s']:.4g} pair-tests/s")
+    # the kernel's own throughput on one batch of the same requests, inputs
+    # and outputs in device memory
+    big = gen.concat(reqs[:80])
+    dq = to_device(big)
+    n_big = int(n_ovl[:80].sum())
+    kb = run_form(ix, dq, dict(mode="fp32_refine", tiling="range", block_size=256), 10, 2, n_big)
     ix.close()
+    log_fn(f"serving: one batch of 80 requests ({len(big)} segments) device-resident: "
+           f"{kb['ms_per_step']:.3f} ms, {kb['value']:.4g} pair-tests/s")
     return dict(workload="C5: 10M-segment Gaussian walk (25,000 x 400) resident; requests of log-uniform "
                          "length 10-5000 (segments of 1/16), d log-uniform in [0.5, 50]; Poisson arrivals",
-                n_requests=n_requests, build_s=round(build_s, 2), saturation_req_s=sat_rate,
-                saturation_pair_tests_s=sat_pairs, saturation_p50_ms=sat["p50_ms"], rates=runs)
+                engine="native scheduler (tds_server_*), fp32_refine, range tiles",
+                streams=streams, n_requests=n_requests, build_s=round(build_s, 2),
+                saturation_req_s=sat_rate, saturation_pair_tests_s=float(n_ovl.sum() / sat["wall_s"]),
+                saturation_p50_ms=sat["p50_ms"], saturation_batches=sat["batches"],
+                saturation_busy_s=sat["busy_s"], device_bytes=sat["device_bytes"],
+                kernel_batch=dict(requests=80, segments=len(big), ms_per_step=kb["ms_per_step"],
+                                  pair_tests_s=kb["value"]),
+                rates=runs)
 
 
 def copy_probe(mib: int):
@@ -460,6 +490,45 @@ def copy_probe(mib: int):
         torch.neg(a, out=b)
     torch.cuda.synchronize()
     log(f"copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches")
+
+
+def valu_probe(log_fn=log):
+    """Issue rates of the vector instructions the pair kernels are built from,
+    measured on this GPU with the probe library (dependence chains of one
+    instruction kind on every SIMD, 8 waves per SIMD), with the shader clock
+    under load from per-wave clock stamps."""
+    import ctypes
+    import torch
+    from paper_1405_7461_amd.build import PROBE_LIB
+    lib = ctypes.CDLL(str(PROBE_LIB))
+    lib.tds_probe_valu.restype = ctypes.c_int
+    lib.tds_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p] + \
+        [ctypes.POINTER(ctypes.c_double)] * 3
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    simds = 4 * cus
+    blocks = cus * 8          # 256-thread blocks: 8 waves per SIMD
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {"simds": simds, "waves_per_simd": 8}
+    names = ("v_sub_f32", "v_max3_f32_abs", "v_min3_f32", "v_fma_f64", "v_add_u32", "v_pk_sub_u16",
+             "v_pk_max_u16", "v_max_f32_e64_abs", "v_pk_add_f16", "v_min_f32", "v_cmp_le_f32")
+    for kind, name in enumerate(names):
+        best = None
+        for _ in range(3):
+            ms, wi, hz = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            rc = lib.tds_probe_valu(kind, blocks, 20000, ctypes.c_void_p(stream), ctypes.byref(ms),
+                                    ctypes.byref(wi), ctypes.byref(hz))
+            assert rc == 0, (name, rc)
+            if best is None or ms.value < best[0]:
+                best = (ms.value, wi.value, hz.value)
+        ms, wi, hz = best
+        rate = wi / (ms / 1e3)                       # wave instructions per second
+        cyc = simds * hz / rate                      # cycles per wave instruction per SIMD
+        out[name] = dict(ms=round(ms, 4), wave_instr=wi, clock_ghz=round(hz / 1e9, 3),
+                         cycles_per_wave_instr=round(cyc, 3), lane_ops_per_s=rate * 64,
+                         lane_ops_per_s_at_2_4ghz=64 * simds * 2.4e9 / cyc)
+        log_fn(f"probe {name}: {cyc:.2f} cycles per wave64 instruction per SIMD at "
+               f"{hz / 1e9:.2f} GHz ({rate * 64:.4g} lane ops/s)")
+    return out
 
 
 def roofline_of(name, r, n_ovl):
@@ -518,6 +587,8 @@ def main():
                     help="skip the response-time model (calibration and predictions)")
     ap.add_argument("--no-tilings", action="store_true",
                     help="skip the at-scale plain batch under the other tilings")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the vector-ALU issue-rate probes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the forms, run a plain device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters)")
@@ -529,6 +600,7 @@ def main():
     if args.headline_only:
         args.no_plain = args.no_host = args.no_batching = args.no_serving = True
         args.no_trajectories = args.no_model = args.no_tilings = args.no_cpu_baseline = True
+        args.no_probe = True
 
     import torch
     import paper_1405_7461_amd as tds
@@ -581,6 +653,8 @@ def main():
         line["host_memory"] = hm
         log(f"C3 {head_name} with host inputs and outputs: {hm['ms_per_step']:.3f} ms/step, "
             f"{hm['value']:.4g} pair-tests/s")
+    if not args.no_probe:
+        line["valu_probe"] = valu_probe()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(db, q, target_s=10.0, label="both d")
         cb["one_core"] = cpu_baseline(db, q, target_s=6.0, nthreads=1, seed=54321, label="both d")

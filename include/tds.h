@@ -52,6 +52,7 @@ extern "C" {
 #define TDS_EDEVICE (-3)   /* a HIP call failed (message names it) */
 #define TDS_EOVERFLOW (-4) /* more selected pairs than the result slabs hold after all retries */
 #define TDS_ESTATE (-5)    /* call out of order (e.g. fetch before a query) */
+#define TDS_EBUSY (-6)     /* serving: the request was refused (its waiting queue is full) */
 
 /* Where the arrays of a tds_segments live. */
 #define TDS_MEM_HOST 0
@@ -373,6 +374,114 @@ int tds_set_allocator(tds_alloc_fn alloc, tds_free_fn free_fn, void *ctx);
 int tds_search_noalloc(const tds_index *ix, const tds_segments *q, const double *d,
                        const tds_query_opts *opts, tds_hit *out, int64_t cap, int64_t *n_total,
                        void *stream);
+
+/*
+ * Grow the query handle's device buffers for batches of up to n_query
+ * segments with `capacity` result selections (counted as in
+ * tds_query_opts.capacity) under the launch shape of `opts` (mode, tiling,
+ * block size, grid, batch size), without running anything. Buffers only
+ * grow, and growing one frees the old buffer, which waits for the whole
+ * device; a serving loop reserves once so that later batches up to that
+ * size never wait for other streams' work. Errors: TDS_EINVAL for null
+ * arguments, negative sizes or bad options; TDS_ESTATE while a batch is
+ * pending; TDS_ENOMEM / TDS_EDEVICE for failed allocations.
+ */
+int tds_query_reserve(tds_query *qh, int64_t n_query, int64_t capacity, const tds_query_opts *opts);
+/* Device bytes the query handle holds (all of its buffers), to *bytes. */
+int tds_query_device_bytes(const tds_query *qh, int64_t *bytes);
+
+/*
+ * Serving (Sec. 3: several users query the resident database at once and
+ * compete for GPU memory; Sec. 5: result memory is reserved before the
+ * kernel runs; Sec. 8: the hit fraction alpha is estimated per temporal
+ * epoch). A server holds an index and `streams` executors, each with its own
+ * HIP stream and query handle. Requests (query segments with a threshold
+ * each, in host memory) are submitted with an arrival time; a scheduler
+ * thread admits arrived requests in arrival order while their estimated
+ * result bytes fit the pool, groups them into one batch per free executor
+ * (continuous batching: requests that arrive while batches run join the
+ * next one) and the executor runs the batch (tds_query_batch +
+ * tds_fetch_results) and splits its hits per request.
+ *
+ * Estimated result bytes of a request = 40 x k_safety x sum over its
+ * segments of alpha(epoch of t_start) x candidate entries (Sec. 4 ranges
+ * from the bin table), with alpha per epoch (`epochs` equal slices of the
+ * database's time extent) a running estimate updated from every completed
+ * batch; waiting requests are re-estimated with the current alpha each time
+ * a batch is formed. The pool counts every executor's device bytes (its
+ * query handle's buffers, which only grow) plus the estimates of the
+ * batches in flight beyond what their executor already holds; a request is
+ * admitted while that total stays within pool_bytes, and a batch of one
+ * request is always admitted when nothing else is in flight (a request
+ * larger than the pool then runs alone). A batch whose estimate was too
+ * small still completes (the library re-runs with more memory).
+ */
+typedef struct {
+    int32_t streams;            /* executors (batches in flight), 1..8; 0 = 4 */
+    int32_t max_batch_segments; /* query segments per batch; 0 = 65,536 */
+    int64_t max_waiting;        /* arrived requests not yet admitted beyond which tds_server_submit
+                                   returns TDS_EBUSY; 0 = no limit */
+    double pool_bytes;          /* device bytes for results across executors; 0 = 256 MiB */
+    double k_safety;            /* multiplier on the estimated hits; 0 = 4 */
+    int32_t epochs;             /* alpha epochs; 0 = 50 */
+    int32_t reserve_segments;   /* segments each executor reserves buffers for at creation; 0 = max_batch_segments */
+    double alpha_prior;         /* alpha before any batch completed; 0 = 1e-4 */
+    tds_query_opts query;       /* options of every batch (capacity is set per batch) */
+} tds_server_opts;
+
+/* Timing and outcome of one request, in seconds on the server's clock
+ * (tds_server_now). */
+typedef struct {
+    double arrival;  /* as submitted */
+    double admit;    /* taken into a batch */
+    double done;     /* its hits are split out and ready */
+    int64_t n_hit;
+    int64_t batch;   /* number of the batch that ran it */
+    int32_t status;  /* TDS_OK, or the error of its batch */
+    int32_t n_batch_requests; /* requests in that batch */
+} tds_request_info;
+
+typedef struct {
+    int64_t batches, requests_done, retries, segments;
+    int64_t device_bytes;  /* executors' device bytes now */
+    double busy_s;         /* executor time spent in batches, summed over executors */
+} tds_server_stats;
+
+typedef struct tds_server tds_server;
+
+/* Create a server over `ix` (which must outlive it); starts its clock and
+ * its threads, and reserves each executor's buffers. Errors: TDS_EINVAL for
+ * null arguments or bad options; TDS_ENOMEM / TDS_EDEVICE. */
+int tds_server_create(tds_index *ix, const tds_server_opts *opts, tds_server **out);
+/* Seconds since the server was created (steady clock). */
+double tds_server_now(const tds_server *srv);
+/*
+ * Submit a request: q (host memory, q->n >= 1 segments) with thresholds d
+ * (host, n values). The arrays are borrowed: they must stay valid and
+ * unchanged until tds_server_wait has returned for the request. The request
+ * becomes visible to the scheduler at `arrival` (server seconds; a time in
+ * the past means now), so an open-loop load can be submitted ahead. *id
+ * receives the request's id (0, 1, ... in submission order). Errors:
+ * TDS_EINVAL for null arguments, n < 1, a non-finite arrival or an invalid
+ * segment or threshold (checked here); TDS_EBUSY when max_waiting arrived
+ * requests already wait; TDS_ESTATE after a failure stopped the server.
+ */
+int tds_server_submit(tds_server *srv, const tds_segments *q, const double *d, double arrival,
+                      int64_t *id);
+/* Wait until request `id` is done (or timeout_s passes; < 0 waits without
+ * limit) and write its info. Returns TDS_OK when done, TDS_ESTATE on
+ * timeout, TDS_EINVAL for an unknown id. */
+int tds_server_wait(tds_server *srv, int64_t id, double timeout_s, tds_request_info *info);
+/* After tds_server_wait: the request's hits (query_idx counts within the
+ * request) to host memory, min(cap, n) records; *n_total gets n. */
+int tds_server_results(tds_server *srv, int64_t id, tds_hit *out, int64_t cap, int64_t *n_total);
+/* Drop a finished request's results (its id stays known). */
+int tds_server_release(tds_server *srv, int64_t id);
+int tds_server_stats_get(const tds_server *srv, tds_server_stats *out);
+/* Current alpha estimate per epoch to host memory (cap values). */
+int tds_server_alpha(const tds_server *srv, double *alpha, int32_t cap, int32_t *n);
+/* Finish every submitted request, stop the threads and free the server. */
+void tds_server_destroy(tds_server *srv);
 
 const char *tds_last_error(void);
 int tds_abi_version(void);

@@ -6,6 +6,7 @@ package is its Python binding. See include/tds.h for the C ABI.
 from .api import (  # noqa: F401
     Hits,
     Index,
+    NativeServer,
     Prepared,
     Query,
     TrajHits,

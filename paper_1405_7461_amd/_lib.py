@@ -18,6 +18,7 @@ TDS_ENOMEM = -2
 TDS_EDEVICE = -3
 TDS_EOVERFLOW = -4
 TDS_ESTATE = -5
+TDS_EBUSY = -6
 
 TDS_MEM_HOST = 0
 TDS_MEM_DEVICE = 1
@@ -87,6 +88,23 @@ class tds_bin(C.Structure):
                 ("last", C.c_int64), ("bin", C.c_int64)]
 
 
+class tds_server_opts(C.Structure):
+    _fields_ = [("streams", C.c_int32), ("max_batch_segments", C.c_int32), ("max_waiting", C.c_int64),
+                ("pool_bytes", C.c_double), ("k_safety", C.c_double), ("epochs", C.c_int32),
+                ("reserve_segments", C.c_int32), ("alpha_prior", C.c_double), ("query", tds_query_opts)]
+
+
+class tds_request_info(C.Structure):
+    _fields_ = [("arrival", C.c_double), ("admit", C.c_double), ("done", C.c_double),
+                ("n_hit", C.c_int64), ("batch", C.c_int64), ("status", C.c_int32),
+                ("n_batch_requests", C.c_int32)]
+
+
+class tds_server_stats(C.Structure):
+    _fields_ = [("batches", C.c_int64), ("requests_done", C.c_int64), ("retries", C.c_int64),
+                ("segments", C.c_int64), ("device_bytes", C.c_int64), ("busy_s", C.c_double)]
+
+
 # name -> (restype, argtypes); every symbol include/tds.h declares
 # tds_alloc_fn / tds_free_fn
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -114,6 +132,17 @@ SIGNATURES = {
     "tds_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "tds_search_noalloc": (C.c_int, [_P, C.POINTER(tds_segments), _P, C.POINTER(tds_query_opts), _P,
                                      C.c_int64, C.POINTER(C.c_int64), _P]),
+    "tds_query_reserve": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(tds_query_opts)]),
+    "tds_query_device_bytes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "tds_server_create": (C.c_int, [_P, C.POINTER(tds_server_opts), C.POINTER(_P)]),
+    "tds_server_now": (C.c_double, [_P]),
+    "tds_server_submit": (C.c_int, [_P, C.POINTER(tds_segments), _P, C.c_double, C.POINTER(C.c_int64)]),
+    "tds_server_wait": (C.c_int, [_P, C.c_int64, C.c_double, C.POINTER(tds_request_info)]),
+    "tds_server_results": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "tds_server_release": (C.c_int, [_P, C.c_int64]),
+    "tds_server_stats_get": (C.c_int, [_P, C.POINTER(tds_server_stats)]),
+    "tds_server_alpha": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_int32)]),
+    "tds_server_destroy": (None, [_P]),
     "tds_last_error": (C.c_char_p, []),
     "tds_abi_version": (C.c_int, []),
 }

@@ -458,3 +458,81 @@ def use_torch_allocator(enable: bool = True) -> None:
     L.check(L.lib().tds_set_allocator(hooks[0], hooks[1], None))
     # keep every registered pair: buffers made by an earlier one free through it
     _torch_hooks = (_torch_hooks or ()) + (hooks,)
+
+
+class NativeServer:
+    """The library's serving runtime (tds_server_*): a scheduler thread and
+    `streams` executors in native code. Requests are host arrays; each is
+    submitted with its arrival time on the server's clock (seconds), and
+    the arrays are kept referenced here until the request is released."""
+
+    def __init__(self, index: Index, streams=4, max_batch_segments=65536, max_waiting=0,
+                 pool_bytes=256 * (1 << 20), k_safety=4.0, epochs=50, reserve_segments=0,
+                 alpha_prior=1e-4, mode="fp32_refine", tiling="range", batch_size=0, block_size=0):
+        q = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0, -1, 0, 0, 0)
+        o = L.tds_server_opts(int(streams), int(max_batch_segments), int(max_waiting), float(pool_bytes),
+                              float(k_safety), int(epochs), int(reserve_segments), float(alpha_prior), q)
+        h = C.c_void_p()
+        L.check(L.lib().tds_server_create(index.handle, C.byref(o), C.byref(h)))
+        self.index = index
+        self._h = h
+        self._keep = {}
+
+    def now(self) -> float:
+        return float(L.lib().tds_server_now(self._h))
+
+    def submit(self, q, d, arrival: float = 0.0) -> int:
+        """Submit host segments q with thresholds d (scalar or per segment);
+        raises TdsError (code TDS_EBUSY) when the waiting queue is full."""
+        s, keep, mem = _segments(q, with_traj=False)
+        if mem != L.TDS_MEM_HOST:
+            raise TypeError("server requests are host arrays")
+        dd = np.ascontiguousarray(np.broadcast_to(np.asarray(d, dtype=np.float64), (int(s.n),)))
+        rid = C.c_int64()
+        L.check(L.lib().tds_server_submit(self._h, C.byref(s), dd.ctypes.data_as(C.c_void_p),
+                                          float(arrival), C.byref(rid)))
+        self._keep[rid.value] = (keep, dd)
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = -1.0) -> dict:
+        info = L.tds_request_info()
+        L.check(L.lib().tds_server_wait(self._h, int(rid), float(timeout), C.byref(info)))
+        return {f: getattr(info, f) for f, _ in L.tds_request_info._fields_}
+
+    def results(self, rid: int) -> Hits:
+        n = C.c_int64()
+        L.check(L.lib().tds_server_results(self._h, int(rid), None, 0, C.byref(n)))
+        buf = np.empty((max(n.value, 1), 5), dtype=np.int64)
+        L.check(L.lib().tds_server_results(self._h, int(rid), buf.ctypes.data_as(C.c_void_p), n.value,
+                                           C.byref(n)))
+        buf = buf[:n.value]
+        return Hits(buf[:, 0].copy(), buf[:, 1].copy(), buf[:, 2].copy(), buf[:, 3].view(np.float64).copy(),
+                    buf[:, 4].view(np.float64).copy())
+
+    def release(self, rid: int) -> None:
+        L.check(L.lib().tds_server_release(self._h, int(rid)))
+        self._keep.pop(int(rid), None)
+
+    def stats(self) -> dict:
+        st = L.tds_server_stats()
+        L.check(L.lib().tds_server_stats_get(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in L.tds_server_stats._fields_}
+
+    def alpha(self) -> np.ndarray:
+        n = C.c_int32()
+        L.check(L.lib().tds_server_alpha(self._h, None, 0, C.byref(n)))
+        a = np.empty(n.value, dtype=np.float64)
+        L.check(L.lib().tds_server_alpha(self._h, a.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        return a
+
+    def close(self):
+        if self._h:
+            L.lib().tds_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

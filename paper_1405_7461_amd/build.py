@@ -23,16 +23,26 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{ROOT / 'include'}",
 ]
-SOURCES = ["tds_kernels.hip", "tds_traj.hip", "tds_greedy.hip", "tds_api.cpp"]
+SOURCES = ["tds_kernels.hip", "tds_traj.hip", "tds_greedy.hip", "tds_api.cpp", "tds_server.cpp"]
+# vector-ALU issue-rate probes for the benchmark's peak figures (own library)
+PROBE_LIB = PKG / "libtds_probe.so"
+PROBE_SOURCES = ["tds_probe.hip"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: Path | None = None) -> Path:
-    """Compile libtds.so (or `out`, with `extra` compiler flags)."""
-    lib = LIB if out is None else Path(out)
-    bdir = BUILD if out is None else lib.parent / (lib.stem + "_build")
+    """Compile libtds.so (or `out`, with `extra` compiler flags); with the
+    default output also the probe library."""
+    if out is None:
+        _link(PROBE_LIB, PROBE_SOURCES, BUILD, verbose, extra)
+        return _link(LIB, SOURCES, BUILD, verbose, extra)
+    lib = Path(out)
+    return _link(lib, SOURCES, lib.parent / (lib.stem + "_build"), verbose, extra)
+
+
+def _link(lib: Path, sources: list[str], bdir: Path, verbose: bool, extra: list[str] | None) -> Path:
     bdir.mkdir(parents=True, exist_ok=True)
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = bdir / (Path(src).stem + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         cmd = [HIPCC, *COMMON, *(extra or []), *lang, "-c", str(CSRC / src), "-o", str(obj)]

@@ -252,6 +252,10 @@ struct Carver {
 
 }  // namespace
 
+namespace tds {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace tds
+
 extern "C" {
 
 const char *tds_last_error(void) { return g_err.c_str(); }
@@ -849,6 +853,53 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     q->traj_valid = false;
     std::memset(&q->stats, 0, sizeof q->stats);
     q->stats.n_query = nq;
+    return TDS_OK;
+}
+
+int tds_query_reserve(tds_query *q, int64_t n_query, int64_t capacity, const tds_query_opts *opts) {
+    if (!q || !opts || n_query < 0 || capacity < 0)
+        return fail(TDS_EINVAL, "tds_query_reserve: invalid argument");
+    if (q->pending) return fail(TDS_ESTATE, "tds_query_reserve: a batch is pending");
+    if (n_query >= (int64_t)INT32_MAX / 2)
+        return fail(TDS_EINVAL, "tds_query_reserve: n_query = %lld out of range", (long long)n_query);
+    tds_segments none{};
+    none.mem = TDS_MEM_DEVICE;
+    tds_query_opts o;
+    int rc = check_batch(&none, nullptr, opts, &o, "tds_query_reserve");
+    if (rc) return rc;
+    const int32_t nq = std::max<int32_t>((int32_t)n_query, 1);
+    const tds_index *ix = q->ix;
+    rc = ensure_capacity(q, nq, nbuckets_for(o.tiling, ix->dev.nb, ix->dev.m));
+    if (rc) return rc;
+    const int kovl = (o.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
+    const int grid = pair_grid(o.mode, o.block_size, o.grid, kovl);
+    if (grid < 1 || (long long)grid * (o.block_size / 64) > INT32_MAX / kSlab)
+        return fail(TDS_EINVAL, "tds_query_reserve: grid %d not supported", grid);
+    const unsigned long long sel = capacity > 0 ? (unsigned long long)capacity : (1ull << 20);
+    rc = ensure_slabs(q, grid * (o.block_size / 64), (sel + kSlab - 1) / kSlab);
+    if (rc) return rc;
+    const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
+    if (greedy || o.tiling == TDS_TILE_PERIODIC) {
+        GreedyBufs gb{};
+        rc = greedy_buffers(q, nq, o.batch_size, o.tiling == TDS_TILE_GREEDY_MAX, greedy, &gb);
+        if (rc) return rc;
+    }
+    // host output is staged on the device: room for `capacity` records
+    HIP_TRY(q->out_stage.ensure((size_t)sel * sizeof(tds_hit)));
+    return TDS_OK;
+}
+
+int tds_query_device_bytes(const tds_query *q, int64_t *bytes) {
+    if (!q || !bytes) return fail(TDS_EINVAL, "tds_query_device_bytes: null argument");
+    size_t t = 0;
+    for (const DBuf *b : {&q->rec, &q->box, &q->first, &q->last, &q->first_s, &q->last_s, &q->key,
+                          &q->perm, &q->qrank, &q->bcount, &q->bj2, &q->bq_off, &q->tiles, &q->units,
+                          &q->unit_off, &q->cost_off, &q->ctr, &q->qstage, &q->cand, &q->hits,
+                          &q->slab_n, &q->slab_h, &q->hit_off, &q->wave_ovl, &q->out_stage,
+                          &q->tr_qtraj, &q->tr_work, &q->tr_temp, &q->tr_out, &q->gs_work,
+                          &q->gs_jump})
+        t += b->bytes;
+    *bytes = (int64_t)t;
     return TDS_OK;
 }
 

@@ -384,5 +384,7 @@ hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const i
                              hipStream_t st);
 int chunk_for(int mode, int block);
 int nbuckets_for(int tiling, int nb, int m);
+// Sets the calling thread's tds_last_error message; returns code.
+int set_error(int code, const char *msg);
 
 }  // namespace tds

@@ -1,0 +1,177 @@
+// Issue-rate probes for the vector ALU of gfx950, used by the benchmark to
+// check the peak rates that the pair kernels are compared against. Not part
+// of the search library: built as its own shared object (libtds_probe.so).
+//
+// Each probe kernel runs dependence chains of one instruction kind (eight
+// independent chains per lane, so a wave always has an instruction ready)
+// on every SIMD of the chip; every wave stamps its start and end with the
+// shader clock (s_memtime) and the constant 100 MHz reference clock
+// (s_memrealtime), so the clock under load is measured alongside the rate.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kChains = 8;
+constexpr int kBlock = 256;
+
+// Per-wave record: shader clock and reference clock at start and end.
+struct Stamp {
+    unsigned long long c0, c1, r0, r1;
+};
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *sink, Stamp *st) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    unsigned long long c0 = __builtin_amdgcn_s_memtime();
+    unsigned long long r0 = __builtin_amdgcn_s_memrealtime();
+    float acc = 0.0f;
+    // The chain steps are written as inline assembly (register operands
+    // only, no memory access) so that exactly the named instruction is timed.
+    if constexpr (KIND <= 2 || (KIND >= 4 && KIND <= 9)) {
+        float a[kChains];
+        float b = seed * 1e-7f + lane * 1e-9f, c = seed * 3e-7f;
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) a[k] = seed + k + lane;
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) {
+                if constexpr (KIND == 0) asm volatile("v_sub_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 1)
+                    asm volatile("v_max3_f32 %0, |%0|, |%1|, |%2|" : "+v"(a[k]) : "v"(b), "v"(c));
+                if constexpr (KIND == 2)
+                    asm volatile("v_min3_f32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+                if constexpr (KIND == 4) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 5) asm volatile("v_pk_sub_u16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 6) asm volatile("v_pk_max_u16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 7)
+                    asm volatile("v_max_f32_e64 %0, |%0|, |%1|" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 8) asm volatile("v_pk_add_f16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 9) asm volatile("v_min_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) acc += a[k];
+    } else if constexpr (KIND == 10) {  // v_cmp_le_f32 into a lane mask, masks combined
+        float a[kChains];
+        float b = seed * 1e-7f + lane * 1e-9f;
+        unsigned long long m = 0;
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) a[k] = seed + k + lane;
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) {
+                unsigned long long r;
+                asm volatile("v_cmp_le_f32_e64 %0, %1, %2" : "=s"(r) : "v"(a[k]), "v"(b));
+                m ^= r;
+            }
+        }
+        acc = (float)(m & 1);
+    } else if constexpr (KIND == 3) {
+        double a[kChains], b = 1.0 + seed * 1e-9, c = seed * 1e-12 + lane * 1e-15;
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) a[k] = seed + k + lane;
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) asm volatile("v_fma_f64 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) s += a[k];
+        acc = (float)s;
+    }
+    // keep the result live; the store is taken only for an impossible value
+    if (acc == -1.2345e-30f) sink[blockIdx.x * kBlock + threadIdx.x] = acc;
+    unsigned long long c1 = __builtin_amdgcn_s_memtime();
+    unsigned long long r1 = __builtin_amdgcn_s_memrealtime();
+    if (lane == 0) st[wave] = Stamp{c0, c1, r0, r1};
+}
+
+template <int KIND>
+hipError_t run_kind(int blocks, int iters, float seed, float *sink, Stamp *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe<KIND>, dim3(blocks), dim3(kBlock), 0, s, iters, seed, sink, st);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+/*
+ * Runs probe `kind` (0 v_sub_f32, 1 v_max3_f32 with absolute-value operands,
+ * 2 v_min3_f32, 3 v_fma_f64, 4 v_add_u32, 5 v_pk_sub_u16, 6 v_pk_max_u16,
+ * 7 v_max_f32 with absolute-value operands (VOP3 form), 8 v_pk_add_f16,
+ * 9 v_min_f32, 10 v_cmp_le_f32 into a lane mask) with `blocks` workgroups of 256
+ * threads, each lane running `iters` iterations of 8 independent chain
+ * steps, on `stream`, and waits for it.
+ * Writes: *ms the kernel's duration (HIP events), *wave_instr the vector
+ * instructions of the measured kind issued (waves x iters x 8), *clock_hz
+ * the shader clock over the run (shader-clock ticks / reference ticks x 1e8,
+ * averaged over the waves). Device memory is allocated and freed inside.
+ * Returns 0, or -3 when a HIP call fails, -1 for a bad argument.
+ */
+int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, double *wave_instr,
+                   double *clock_hz) {
+    if (kind < 0 || kind > 10 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
+    hipStream_t s = (hipStream_t)stream;
+    const int waves = blocks * (kBlock / 64);
+    float *sink = nullptr;
+    Stamp *st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = -3;
+    if (hipMalloc(&sink, sizeof(float) * (size_t)blocks * kBlock) != hipSuccess) return -3;
+    if (hipMalloc(&st, sizeof(Stamp) * (size_t)waves) != hipSuccess) goto done;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+    {
+        const float seed = 1.5f;
+        hipError_t err = hipEventRecord(e0, s);
+        if (err == hipSuccess) {
+            switch (kind) {
+            case 0: err = run_kind<0>(blocks, iters, seed, sink, st, s); break;
+            case 1: err = run_kind<1>(blocks, iters, seed, sink, st, s); break;
+            case 2: err = run_kind<2>(blocks, iters, seed, sink, st, s); break;
+            case 3: err = run_kind<3>(blocks, iters, seed, sink, st, s); break;
+            case 4: err = run_kind<4>(blocks, iters, seed, sink, st, s); break;
+            case 5: err = run_kind<5>(blocks, iters, seed, sink, st, s); break;
+            case 6: err = run_kind<6>(blocks, iters, seed, sink, st, s); break;
+            case 7: err = run_kind<7>(blocks, iters, seed, sink, st, s); break;
+            case 8: err = run_kind<8>(blocks, iters, seed, sink, st, s); break;
+            case 9: err = run_kind<9>(blocks, iters, seed, sink, st, s); break;
+            default: err = run_kind<10>(blocks, iters, seed, sink, st, s); break;
+            }
+        }
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) goto done;
+        Stamp *h = new Stamp[waves];
+        if (hipMemcpy(h, st, sizeof(Stamp) * (size_t)waves, hipMemcpyDeviceToHost) != hipSuccess) {
+            delete[] h;
+            goto done;
+        }
+        double f = 0.0;
+        int nf = 0;
+        for (int w = 0; w < waves; ++w) {
+            const double dr = (double)(h[w].r1 - h[w].r0);
+            if (dr > 0) {
+                f += (double)(h[w].c1 - h[w].c0) / dr * 1e8;
+                ++nf;
+            }
+        }
+        delete[] h;
+        *ms = t;
+        *wave_instr = (double)waves * iters * kChains;
+        *clock_hz = nf ? f / nf : 0.0;
+        rc = 0;
+    }
+done:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipFree(st);
+    (void)hipFree(sink);
+    return rc;
+}
+
+}  // extern "C"

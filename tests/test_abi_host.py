@@ -191,3 +191,32 @@ def test_plan_ranges_equal_oracle(seed):
             j2 = np.searchsorted(bins["start"], qb[i], side="left") - 1
             differs += int(r is not None and bins["last"][j2] != r[1])
     assert differs > 0  # the case where the two readings part is exercised
+
+
+def test_server_and_reserve_arguments():
+    # the serving and reservation entry points reject bad arguments before any
+    # device work
+    import ctypes as C
+    lib = L.lib()
+    assert C.sizeof(L.tds_server_opts) == 48 + C.sizeof(L.tds_query_opts)
+    assert C.sizeof(L.tds_request_info) == 48
+    assert C.sizeof(L.tds_server_stats) == 48
+    opts = L.tds_query_opts(L.TDS_MODE_FP64, L.TDS_TILE_RANGE, 0, 0, 0, -1, 0, 0, 0)
+    assert lib.tds_query_reserve(None, 10, 10, C.byref(opts)) == L.TDS_EINVAL
+    assert b"tds_query_reserve" in lib.tds_last_error()
+    n = C.c_int64()
+    assert lib.tds_query_device_bytes(None, C.byref(n)) == L.TDS_EINVAL
+    so = L.tds_server_opts()
+    h = C.c_void_p()
+    assert lib.tds_server_create(None, C.byref(so), C.byref(h)) == L.TDS_EINVAL
+    assert b"tds_server_create" in lib.tds_last_error()
+    rid = C.c_int64()
+    assert lib.tds_server_submit(None, None, None, 0.0, C.byref(rid)) == L.TDS_EINVAL
+    assert lib.tds_server_wait(None, 0, 0.0, C.byref(L.tds_request_info())) == L.TDS_EINVAL
+    assert lib.tds_server_results(None, 0, None, 0, C.byref(n)) == L.TDS_EINVAL
+    assert lib.tds_server_release(None, 0) == L.TDS_EINVAL
+    assert lib.tds_server_stats_get(None, C.byref(L.tds_server_stats())) == L.TDS_EINVAL
+    m = C.c_int32()
+    assert lib.tds_server_alpha(None, None, 0, C.byref(m)) == L.TDS_EINVAL
+    assert lib.tds_server_now(None) == 0.0
+    lib.tds_server_destroy(None)  # a null server is ignored
