@@ -42,21 +42,23 @@ METRIC = "segment-pair tests/s + p99 query latency; FP32+FP64-refine vs FP64, ex
 D_VALUES = (1.0, 5.0, 25.0)      # the at-scale plain workload
 NUM_BINS = 1000
 HEAD_D = (0.001, 0.01)           # the precision-form workload
+PLAIN_WORKLOAD = ("C2 plain at scale: 1M-segment Gaussian random walk (2,500 x 400), "
+                  "40,000 query segments x d in {1,5,25} (120,000 per step), 1,000 bins")
 HEAD_WORKLOAD = ("C3 precision form: 5M segments on Plummer-sphere circular orbits (10,000 x 500), "
                  "100,000 query segments x d in {0.001, 0.01} (200,000 per step), 500 bins")
 
 # MI355X peaks (published figures, and the unit counts behind them): binary32
-# vector 157.3 TFLOP/s counts an FMA as 2 flops, i.e. 78.6e12 binary32 VALU
-# operations/s = 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz; binary64 vector
-# 78.6 TFLOP/s (FMA = 2), i.e. 39.3e12 binary64 operations/s.
-FP32_OPS_PEAK = 256 * 4 * 32 * 2.4e9
+# vector 157.3 TFLOP/s = 256 CUs x 4 SIMDs x 32 lanes x 2 flops (FMA) x 2.4 GHz,
+# which non-packed binary32 multiply-adds reach (the issue-rate probe measures
+# v_fmac_f32 at 2.4 cycles per wave64 instruction); binary64 vector 78.6
+# TFLOP/s = 16 lanes x 2 flops per SIMD-cycle (v_fma_f64 at 4.4 cycles).
+FP32_PEAK = 157.3e12
 FP64_PEAK = 78.6e12
 # Algorithmic work per pair:
 FP64_FLOPS_PER_PAIR = 49          # binary64 decision per overlapping pair, FMA = 2
-# binary32 box test per candidate pair: three subtractions, one three-way
-# maximum of their absolute values (absolute value is an operand modifier),
-# one comparison with the threshold
-FILTER_OPS_PER_PAIR = 5
+# binary32 ball test per candidate pair: s = e2 + (-2C).c as three
+# multiply-adds (6 flops) and its comparison with the query's threshold
+FILTER_FLOPS_PER_PAIR = 7
 
 
 def log(*a):
@@ -510,7 +512,9 @@ def valu_probe(log_fn=log):
     stream = torch.cuda.current_stream().cuda_stream
     out = {"simds": simds, "waves_per_simd": 8}
     names = ("v_sub_f32", "v_max3_f32_abs", "v_min3_f32", "v_fma_f64", "v_add_u32", "v_pk_sub_u16",
-             "v_pk_max_u16", "v_max_f32_e64_abs", "v_pk_add_f16", "v_min_f32", "v_cmp_le_f32")
+             "v_pk_max_u16", "v_max_f32_e64_abs", "v_pk_add_f16", "v_min_f32", "v_cmp_le_f32",
+             "v_fma_f32", "v_fmac_f32", "v_mul_f32", "v_add_f32", "v_or_b32", "v_or3_b32", "v_max_f32",
+             "v_sub_f32_e64_abs")
     for kind, name in enumerate(names):
         best = None
         for _ in range(3):
@@ -534,10 +538,11 @@ def valu_probe(log_fn=log):
 def roofline_of(name, r, n_ovl):
     """Roofline of a form's pair kernel from its HIP-event launch time."""
     if name == "fp32_refine":
-        ach = FILTER_OPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3)
-        return dict(bound="alu", achieved=ach / 1e12, peak=FP32_OPS_PEAK / 1e12, unit="TOP/s",
-                    frac=ach / FP32_OPS_PEAK, kernel="k_pair<fp32_refine>",
-                    per_unit=f"{FILTER_OPS_PER_PAIR} binary32 operations per candidate pair",
+        ach = FILTER_FLOPS_PER_PAIR * r["n_eval"] / (r["pair_ms"] / 1e3)
+        return dict(bound="alu", achieved=ach / 1e12, peak=FP32_PEAK / 1e12, unit="TFLOP/s",
+                    frac=ach / FP32_PEAK, kernel="k_pair<fp32_refine>",
+                    per_unit=f"{FILTER_FLOPS_PER_PAIR} binary32 flops per candidate pair (three "
+                             "multiply-adds, FMA = 2, and the threshold comparison)",
                     units_per_launch=r["n_eval"], launch_ms=r["pair_ms"])
     ach = FP64_FLOPS_PER_PAIR * n_ovl / (r["pair_ms"] / 1e3)
     return dict(bound="alu", achieved=ach / 1e12, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
@@ -578,6 +583,9 @@ def main():
     ap.add_argument("--forms", default="fp32_refine,fp64")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline workload's forms (for profiler runs)")
+    ap.add_argument("--workload", default="C3", choices=("C3", "C2"),
+                    help="workload of the headline forms: the precision form (default) or, for "
+                         "profiling, the at-scale plain workload")
     ap.add_argument("--no-plain", action="store_true", help="skip the at-scale plain workload")
     ap.add_argument("--no-host", action="store_true", help="skip the host-memory (PCIe) steps")
     ap.add_argument("--no-batching", action="store_true")
@@ -609,7 +617,7 @@ def main():
 
     # ------------------------------------------------ headline: precision form
     t0 = time.perf_counter()
-    db, q, m = make_workload("C3")
+    db, q, m = make_workload(args.workload)
     n_ovl = overlap_count(db, q)
     log(f"headline workload: {len(db)} entries, {len(q)} query segments, N_ovl={n_ovl} "
         f"({time.perf_counter() - t0:.1f} s to generate)")
@@ -618,13 +626,14 @@ def main():
     log(f"index built in {time.perf_counter() - t0:.2f} s: {ix.info()}")
     dq = to_device(q)
     torch.cuda.synchronize()
-    results, forms = time_forms(ix, dq, n_ovl, args.forms.split(","), args.steps, args.warmup, "C3")
+    results, forms = time_forms(ix, dq, n_ovl, args.forms.split(","), args.steps, args.warmup, args.workload)
     if args.copy_probe:
         copy_probe(args.copy_probe)
     head_name = "fp32_refine" if "fp32_refine" in results else list(results)[0]
     head = results[head_name]
     roof = dict(head["roofline"])
-    roof["traffic"] = measured_traffic(f"k_pair_{'fp32' if head_name == 'fp32_refine' else 'fp64'}_c3_hbm.txt")
+    roof["traffic"] = measured_traffic(f"k_pair_{'fp32' if head_name == 'fp32_refine' else 'fp64'}_"
+                                       f"{args.workload.lower()}_hbm.txt")
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
     line = {
         "metric": METRIC,
@@ -639,7 +648,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if head_name == "fp32_refine" else "f64",
         "data": "synthetic",
-        "config": {"workload": HEAD_WORKLOAD, "form": head_name, "n_overlap_per_step": n_ovl,
+        "config": {"workload": HEAD_WORKLOAD if args.workload == "C3" else PLAIN_WORKLOAD, "form": head_name,
+                   "n_overlap_per_step": n_ovl,
                    **{k: v for k, v in head["opts"].items()}},
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
         "roofline": roof,
@@ -671,8 +681,7 @@ def main():
         ix2 = tds.build_index(db2, m2)
         dq2 = to_device(q2)
         r2, forms2 = time_forms(ix2, dq2, n2, ["fp32_refine", "fp64"], args.steps, args.warmup, "C2")
-        line["plain"] = dict(workload="C2 plain at scale: 1M-segment Gaussian random walk (2,500 x 400), "
-                                      "40,000 query segments x d in {1,5,25} (120,000 per step), 1,000 bins",
+        line["plain"] = dict(workload=PLAIN_WORKLOAD,
                              n_overlap_per_step=n2, forms=_strip(r2))
         if not args.no_tilings:
             line["tilings"] = tiling_comparison(ix2, dq2, n2)

@@ -171,7 +171,8 @@ struct tds_index {
     int32_t m = 0;
     double t_first = 0, t_last = 0, width = 1;
     std::vector<tds_bin> bins;
-    DBuf t0, t1, x0, y0, z0, vx, vy, vz, ecen, orig, traj, t1s;
+    DBuf t0, t1, x0, y0, z0, vx, vy, vz, ecen, erad, orig, traj, t1s;
+    double ox = 0, oy = 0, oz = 0;  // origin of the binary32 coordinates
     DBuf bstart, bpend, bfirst, blast, btree;
     DevIndex dev{};
     int64_t device_bytes = 0;
@@ -372,6 +373,21 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     plan_bins(t0s.data(), t1p.data(), n, opts->num_bins, &ix->bins, &ix->t_first, &ix->t_last,
               &ix->width);
     const int64_t nb = (int64_t)ix->bins.size();
+    // Origin of the binary32 coordinates: the per-axis median of the end
+    // points (robust to a few far outliers), so that |c| stays near the data's
+    // own extent and the binary32 test's rounding bound with it.
+    if (n > 0) {
+        std::vector<double> v((size_t)2 * n);
+        double *org[3] = {&ix->ox, &ix->oy, &ix->oz};
+        for (int k = 0; k < 3; ++k) {
+            for (int64_t i = 0; i < n; ++i) {
+                v[(size_t)2 * i] = h[k][i];
+                v[(size_t)2 * i + 1] = h[k + 4][i];
+            }
+            std::nth_element(v.begin(), v.begin() + n, v.end());
+            *org[k] = v[(size_t)n];
+        }
+    }
 
     auto cleanup = [&](int code) {
         tds_index_destroy(ix);
@@ -390,6 +406,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
                     &ix->traj, &ix->t1s})
         IX_TRY(b->ensure(n1 * 8));
     IX_TRY(ix->ecen.ensure(n1 * 16));
+    IX_TRY(ix->erad.ensure(n1 * 4));
     IX_TRY(ix->orig.ensure(n1 * 4));
     const size_t nb1 = (size_t)std::max<int64_t>(nb, 1);
     IX_TRY(ix->bstart.ensure(nb1 * 8));
@@ -436,8 +453,9 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
         IX_TRY(launch_ingest(rawp, n, dperm.as<int32_t>(), traj_dev, ix->t0.as<double>(),
                              ix->t1.as<double>(), ix->x0.as<double>(), ix->y0.as<double>(),
                              ix->z0.as<double>(), ix->vx.as<double>(), ix->vy.as<double>(),
-                             ix->vz.as<double>(), ix->ecen.as<float4>(),
-                             ix->orig.as<int32_t>(), ix->traj.as<int64_t>(), st));
+                             ix->vz.as<double>(), ix->ecen.as<float4>(), ix->erad.as<float>(),
+                             ix->ox, ix->oy, ix->oz, ix->orig.as<int32_t>(),
+                             ix->traj.as<int64_t>(), st));
         IX_TRY(hipMemcpyAsync(ix->t1s.p, t1s.data(), n * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->bstart.p, bs.data(), nb * 8, hipMemcpyHostToDevice, st));
         IX_TRY(hipMemcpyAsync(ix->bpend.p, bp.data(), nb * 8, hipMemcpyHostToDevice, st));
@@ -466,6 +484,10 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.vy = ix->vy.as<double>();
     d.vz = ix->vz.as<double>();
     d.ecen = ix->ecen.as<float4>();
+    d.erad = ix->erad.as<float>();
+    d.ox = ix->ox;
+    d.oy = ix->oy;
+    d.oz = ix->oz;
     d.orig = ix->orig.as<int32_t>();
     d.traj = ix->traj.as<int64_t>();
     d.t1s = ix->t1s.as<double>();
@@ -476,7 +498,7 @@ int tds_build_index(const tds_segments *db, const tds_index_opts *opts, void *st
     d.btree = ix->btree.as<double>();
     d.bleaf = tree_leaves(nb);
     d.pad_b = 0;
-    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 4 + 8 + 8) + nb * 24 + (int64_t)bt.size() * 8);
+    ix->device_bytes = (int64_t)(n * (8 * 8 + 16 + 4 + 4 + 8 + 8) + nb * 24 + (int64_t)bt.size() * 8);
     *out = ix;
     return TDS_OK;
 }
@@ -513,7 +535,7 @@ int tds_index_times(const tds_index *ix, double *t_start_sorted, double *t_end_s
 void tds_index_destroy(tds_index *ix) {
     if (!ix) return;
     for (DBuf *b : {&ix->t0, &ix->t1, &ix->x0, &ix->y0, &ix->z0, &ix->vx, &ix->vy, &ix->vz,
-                    &ix->ecen, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
+                    &ix->ecen, &ix->erad, &ix->orig, &ix->traj, &ix->t1s, &ix->bstart, &ix->bpend,
                     &ix->bfirst, &ix->blast, &ix->btree})
         b->release();
     delete ix;

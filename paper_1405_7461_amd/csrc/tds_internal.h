@@ -19,9 +19,10 @@ struct QRec64 {
     double pad;
 };
 
-// Conservative binary32 region of a query segment: the cube of half-width r
-// about (cx, cy, cz) that contains its bounding box widened by d + band on
-// every axis, with the slack the binary32 test needs (16 bytes).
+// Conservative binary32 region of a query segment: the ball of radius r
+// about (cx, cy, cz) (relative to the index origin) that contains every point
+// within d + band of the segment, with the slack the binary32 test needs
+// (16 bytes).
 struct alignas(16) QCube32 {
     float cx, cy, cz, r;
 };
@@ -222,8 +223,10 @@ struct DevIndex {
     int32_t m;   // bins as requested
     double t_first, width;
     const double *t0, *t1, *x0, *y0, *z0, *vx, *vy, *vz;
-    const float4 *ecen;   // entry box centre and largest half-width h: the cube
-                          // [c - h, c + h]^3 contains the segment
+    const float4 *ecen;   // entry ball in binary32 relative to the origin: centre c
+                          // (the segment's midpoint) and e2 = |c|^2 (rounded)
+    const float *erad;    // entry ball radius: half the segment's length plus the
+                          // entry's share of the error band and of c's rounding
     const int32_t *orig;  // caller index of each sorted entry
     const int64_t *traj;  // trajectory id of each sorted entry
     const double *t1s;    // t_end, sorted independently (overlap counts)
@@ -232,6 +235,8 @@ struct DevIndex {
     const double *btree;  // max-tree of the bin ends (2 * bleaf values)
     int32_t bleaf;        // leaves of btree: the smallest power of two >= nb
     int32_t pad_b;
+    double ox, oy, oz;    // origin of the binary32 coordinates (per-axis median of
+                          // the database's end points)
 };
 
 // Error band of the binary32 filter. A binary64 hit of a pair implies that
@@ -249,6 +254,19 @@ struct DevIndex {
 constexpr double kBandRel = 0x1p-20;
 constexpr double kBandAbs = 0x1p-40;
 constexpr double kCmpSlack = 0x1p-20;
+// The binary32 test of a query ball (centre C, radius r) against the entries
+// of a chunk (centres c, radii at most H) passes a pair when
+//   s = e2 + (-2C).c <= T = (r + H)^2 - |C|^2 + kDotSlack (e2max + |C|^2),
+// s evaluated as one multiply-add per axis; |C - c|^2 = |c|^2 - 2C.c + |C|^2,
+// and the rounding of e2 and of the three multiply-adds is at most
+// 4 * 2^-24 (|c|^2 + 2|c||C|) <= 2^-21 (e2max + |C|^2) (with e2max the largest
+// e2 of the chunk), half of kDotSlack. T is evaluated in binary64 and rounded
+// up to binary32, so balls that meet always pass.
+constexpr double kDotSlack = 0x1p-20;
+// Coordinates relative to the origin (and radii) up to this magnitude take
+// part in the binary32 test (|c|^2 and 2|C||c| stay far below the binary32
+// range); beyond it an entry or query passes every pair.
+constexpr double kSphereLimit = 0x1p60;
 
 // Range buckets per first candidate bin: spans of 0, 1, 2 and >= 3 bins.
 constexpr int kSpanClasses = 4;
@@ -303,6 +321,10 @@ struct TrajKey {
 // Merges of at most this many hits sort TrajKey records once with a
 // comparison merge sort; larger ones use three stable radix sorts.
 constexpr long long kTrajOneSortMax = 1LL << 16;
+// Merges of at most this many hits rank each key by counting the keys that
+// precede it (n^2 comparisons spread over the whole GPU), scatter, and merge
+// in one workgroup: four launches instead of a dozen.
+constexpr long long kTrajRankMax = 8192;
 
 // t_b with a pair-start flag: the element of the segmented running maximum.
 struct SegMax {
@@ -346,7 +368,8 @@ struct GreedyBufs {
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
                          double *z0, double *vx, double *vy, double *vz, float4 *ecen,
-                         int32_t *orig, int64_t *traj, hipStream_t st);
+                         float *erad, double ox, double oy, double oz, int32_t *orig,
+                         int64_t *traj, hipStream_t st);
 // ev_start (optional) records the start of the first kernel.
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
                           hipStream_t st, hipEvent_t ev_start = nullptr);

@@ -54,16 +54,6 @@ __device__ __forceinline__ float f32_up(double x) {
     return ((double)f < x) ? nextafterf(f, INFINITY) : f;
 }
 
-// Interval [lo, hi] as a binary32 centre c and half-width h with
-// [c - h, c + h] containing it (h rounded up from the binary64 difference).
-__device__ __forceinline__ void centre_half(double lo, double hi, float &c, float &h) {
-    c = (float)(0.5 * lo + 0.5 * hi);
-    const double cd = (double)c;
-    h = f32_up(dmx(hi - cd, cd - lo));
-}
-// Coordinates (and query half-widths) up to this magnitude take part in the
-// binary32 test; beyond it a region is made unbounded so that it passes.
-constexpr double kCubeLimit = 0x1p100;
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -73,8 +63,32 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // --------------------------------------------------------------- ingest
+// Ball of a segment for the binary32 test, relative to the origin (ox, oy,
+// oz): centre c = the midpoint rounded to binary32, and a radius that holds
+// the whole segment around c (half its length plus the distance from the
+// exact midpoint to c), widened by `widen` and by kCmpSlack of itself, rounded
+// up. Returns false when the ball is beyond the binary32 test's range.
+__device__ __forceinline__ bool segment_ball(double a0, double b0, double c0, double a1, double b1,
+                                             double c1, double ox, double oy, double oz,
+                                             double widen, float &cx, float &cy, float &cz,
+                                             float &r) {
+    const double mx = 0.5 * (a0 + a1) - ox, my = 0.5 * (b0 + b1) - oy, mz = 0.5 * (c0 + c1) - oz;
+    const double dx = a1 - a0, dy = b1 - b0, dz = c1 - c0;
+    const double half = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+    const double reach = dmx(dmx(fabs(mx), fabs(my)), fabs(mz)) + half + widen;
+    if (!(reach <= kSphereLimit)) return false;
+    cx = (float)mx;
+    cy = (float)my;
+    cz = (float)mz;
+    // m - c is exact in binary64 (c is m rounded to 24 bits)
+    const double ex = mx - (double)cx, ey = my - (double)cy, ez = mz - (double)cz;
+    const double rr = half + sqrt(ex * ex + ey * ey + ez * ez) + widen;
+    r = f32_up(rr + kCmpSlack * rr);
+    return true;
+}
+
 // One thread per sorted position p: gather the caller's segment perm[p],
-// compute its velocity and its conservative binary32 bounding box.
+// compute its velocity and its conservative binary32 ball.
 __global__ void k_ingest(const double *__restrict__ rx0, const double *__restrict__ ry0,
                          const double *__restrict__ rz0, const double *__restrict__ rt0,
                          const double *__restrict__ rx1, const double *__restrict__ ry1,
@@ -82,7 +96,8 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
                          int64_t n, const int32_t *__restrict__ perm,
                          const int64_t *__restrict__ traj_raw, double *t0, double *t1, double *x0,
                          double *y0, double *z0, double *vx, double *vy, double *vz, float4 *ecen,
-                         int32_t *orig, int64_t *traj) {
+                         float *erad, double ox, double oy, double oz, int32_t *orig,
+                         int64_t *traj) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int32_t i = perm[p];
@@ -97,21 +112,21 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
     vx[p] = (a1 - a0) / dt;
     vy[p] = (b1 - b0) / dt;
     vz[p] = (c1 - c0) / dt;
-    float cx, cy, cz, hx, hy, hz, h;
+    // the entry's share of the error band (magnitude of its own coordinates)
     const double mag = dmx(dmx(dmx(fabs(a0), fabs(a1)), dmx(fabs(b0), fabs(b1))), dmx(fabs(c0), fabs(c1)));
-    if (mag <= kCubeLimit) {
-        centre_half(dmn(a0, a1), dmx(a0, a1), cx, hx);
-        centre_half(dmn(b0, b1), dmx(b0, b1), cy, hy);
-        centre_half(dmn(c0, c1), dmx(c0, c1), cz, hz);
-        // the entry's share of the error band and of the comparison's slack
-        const double ext = fabs(a1 - a0) + fabs(b1 - b0) + fabs(c1 - c0);
-        const double hm = (double)fmaxf(fmaxf(hx, hy), hz);
-        h = f32_up(hm + kBandRel * ext + kBandAbs * (mag + ext) + kCmpSlack * hm);
-    } else {  // beyond the binary32 test's range: an unbounded box passes every query
-        cx = cy = cz = 0.0f;
-        h = INFINITY;
+    const double ext = fabs(a1 - a0) + fabs(b1 - b0) + fabs(c1 - c0);
+    float cx, cy, cz, r;
+    float4 e;
+    if (segment_ball(a0, b0, c0, a1, b1, c1, ox, oy, oz, kBandRel * ext + kBandAbs * (mag + ext), cx,
+                     cy, cz, r)) {
+        const double e2 = (double)cx * cx + (double)cy * cy + (double)cz * cz;
+        e = make_float4(cx, cy, cz, (float)e2);
+    } else {  // beyond the binary32 test's range: s = -inf passes every query
+        e = make_float4(0.0f, 0.0f, 0.0f, -INFINITY);
+        r = 0.0f;
     }
-    ecen[p] = make_float4(cx, cy, cz, h);
+    ecen[p] = e;
+    erad[p] = r;
     orig[p] = i;
     traj[p] = traj_raw ? traj_raw[i] : (int64_t)i;
 }
@@ -119,13 +134,14 @@ __global__ void k_ingest(const double *__restrict__ rx0, const double *__restric
 hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *perm_sorted,
                          const int64_t *traj_raw, double *t0, double *t1, double *x0, double *y0,
                          double *z0, double *vx, double *vy, double *vz, float4 *ecen,
-                         int32_t *orig, int64_t *traj, hipStream_t st) {
+                         float *erad, double ox, double oy, double oz, int32_t *orig,
+                         int64_t *traj, hipStream_t st) {
     if (n == 0) return hipSuccess;
     int blk = 256;
     int64_t grid = (n + blk - 1) / blk;
     hipLaunchKernelGGL(k_ingest, dim3((unsigned)grid), dim3(blk), 0, st, raw[0], raw[1], raw[2],
                        raw[3], raw[4], raw[5], raw[6], raw[7], n, perm_sorted, traj_raw, t0, t1, x0,
-                       y0, z0, vx, vy, vz, ecen, orig, traj);
+                       y0, z0, vx, vy, vz, ecen, erad, ox, oy, oz, orig, traj);
     TDS_LAUNCH_CHECK();
 }
 
@@ -227,24 +243,17 @@ __global__ void k_qprep(const double *__restrict__ qx0, const double *__restrict
         r.pad = 0.0;
         b.rec[i] = r;
 
-        // Box widened by d plus the query's share of the error band (the
-        // binary64 decision's own rounding and that of computed positions).
+        // Ball of the segment widened by d plus the query's share of the
+        // error band (the binary64 decision's own rounding and that of
+        // computed positions): every point within d of the segment lies in
+        // it. An entry ball of radius r_e that it does not meet holds no
+        // point of the entry segment, so no hit.
         double ext = fabs(a1 - a0) + fabs(b1 - b0) + fabs(c1 - c0);
         double mag = dmx(dmx(fabs(a0), fabs(a1)), dmx(dmx(fabs(b0), fabs(b1)), dmx(fabs(c0), fabs(c1))));
         double w = d + kBandRel * (d + ext) + kBandAbs * (1.0 + d + mag + ext);
-        // The widened box as a cube: centre C and the largest half-width r,
-        // plus the comparison's slack. The binary32 test compares
-        // max_axis |c - C| with r + H (H the largest entry half-width of a
-        // chunk, band included).
         QCube32 bx;
-        if (mag + w <= kCubeLimit) {
-            float hx, hy, hz;
-            centre_half(dmn(a0, a1) - w, dmx(a0, a1) + w, bx.cx, hx);
-            centre_half(dmn(b0, b1) - w, dmx(b0, b1) + w, bx.cy, hy);
-            centre_half(dmn(c0, c1) - w, dmx(c0, c1) + w, bx.cz, hz);
-            const double r = dmx(dmx((double)hx, (double)hy), (double)hz);
-            bx.r = f32_up(r + kCmpSlack * r);
-        } else {  // beyond the binary32 test's range: pass every entry
+        if (!segment_ball(a0, b0, c0, a1, b1, c1, ix.ox, ix.oy, ix.oz, w, bx.cx, bx.cy, bx.cz, bx.r)) {
+            // beyond the binary32 test's range: pass every entry
             bx.cx = bx.cy = bx.cz = 0.0f;
             bx.r = INFINITY;
         }
@@ -719,23 +728,21 @@ __device__ __forceinline__ int tile_of_unit(const long long *__restrict__ off, i
     return lo;
 }
 
-// Conservative binary32 test: do the entry's box and the query's cube (its
-// box widened by d + band, with rounding slack) overlap on every axis?
-// Largest per-axis gap |c - C| - h between an entry box (centre c, half-
-// widths h) and a query centre C: the pair passes when it is <= the query's
-// r. NaN (an empty slot) never passes.
-// Largest axis distance between an entry box centre and a query cube
-// centre: three subtractions and one max3 with absolute-value modifiers.
-// The caller compares it with r + H, H the largest half-width of the
-// entries in the chunk (wave-uniform), which holds whenever some entry box
-// of the chunk meets the cube, so the test stays conservative with four
-// instructions per pair instead of seven for per-entry half-widths.
-__device__ __forceinline__ float cube_gap(const float4 &c, const float4 &q) {
-    return fmaxf(fmaxf(fabsf(c.x - q.x), fabsf(c.y - q.y)), fabsf(c.z - q.z));
-}
-
-// Query boxes staged in LDS per wave: 64 at a time, one per lane.
+// Conservative binary32 test (the ball of every point within d + band of the
+// query segment against the ball that holds an entry segment): with centres
+// C and c relative to the index origin, |C - c|^2 = |c|^2 - 2C.c + |C|^2, so
+// per pair the test costs three multiply-adds, s = e2 + (-2C).c, compared
+// with a per-query threshold T that takes the chunk's largest entry radius
+// H and the rounding bound (kDotSlack). Multiply-adds issue at twice the rate
+// of the minimum, maximum and compare instructions on gfx950, which a
+// box test (three differences and a three-way maximum per pair) needs.
+// Query balls staged in LDS per wave: 64 at a time, one per lane.
 constexpr int kStage = 64;
+// Staged queries tested between two branches of the binary32 walk.
+#ifndef TDS_GROUP
+#define TDS_GROUP 2
+#endif
+constexpr int kGroup = TDS_GROUP;
 
 // Wave priority for the SIMD's instruction arbiter (0 lowest .. 3 highest).
 __device__ __forceinline__ void set_prio(int p) {
@@ -751,7 +758,10 @@ __device__ __forceinline__ void set_prio(int p) {
 #ifndef TDS_EPT32
 #define TDS_EPT32 4
 #endif
-constexpr int ept_for_mode(int mode) { return mode == kModeFP64 ? 2 : TDS_EPT32; }
+#ifndef TDS_EPT64
+#define TDS_EPT64 2
+#endif
+constexpr int ept_for_mode(int mode) { return mode == kModeFP64 ? TDS_EPT64 : TDS_EPT32; }
 int chunk_for(int mode, int) { return 64 * ept_for_mode(mode); }
 
 __device__ __forceinline__ long long rfl64(long long v) {
@@ -824,9 +834,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
     };
     // progress-based wave priority (see below): one step down per pr_step units
     int prio = 3, pr_step = 1, pr_next = 1;
-    auto progress = [&]() {
-        if (--pr_next == 0) {
-            pr_next = pr_step;
+    auto progress = [&](int units) {
+        pr_next -= units;
+        if (pr_next <= 0) {
+            pr_next += pr_step;
             if (prio > 0) set_prio(--prio);
         }
     };
@@ -883,7 +894,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         const int pn = pnext;
                         pnext = perm[qs + 2];
                         qn = rec[clampq(pn)];
-                        progress();
+                        progress(1);
 #pragma unroll
                         for (int j = 0; j < EPT; ++j) {
                             if (!FULL && j >= nv) break;  // wave-uniform
@@ -899,46 +910,54 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 else
                     walk(std::false_type{});
             } else {
-                // Conservative binary32 filter: the entry's box against the
-                // query's cube; time is left to the refine.
+                // Conservative binary32 filter: the entry's ball against the
+                // query's ball; time is left to the refine. Each slot holds
+                // (c, e2) of an entry, or NaN for no entry (NaN never passes).
                 float4 ec[EPT];
-                float hmax = 0.0f;
+                float hmax = 0.0f, e2max = 0.0f;
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) {
                     const int e = wb + j * 64 + lane;
                     if (e < we) {
                         ec[j] = ix.ecen[e];
-                        hmax = fmaxf(hmax, ec[j].w);
-                    } else {  // an empty slot (NaN) never passes
-                        ec[j] = make_float4(NAN, NAN, NAN, NAN);
+                        e2max = fmaxf(e2max, ec[j].w);
+                        hmax = fmaxf(hmax, ix.erad[e]);
+                    } else {
+                        ec[j] = make_float4(0.0f, 0.0f, 0.0f, NAN);
                     }
                 }
-                // H: the largest entry half-width of the chunk (wave-uniform)
-                for (int off = 32; off > 0; off >>= 1) hmax = fmaxf(hmax, __shfl_xor(hmax, off));
+                // H: the largest entry radius of the chunk, E2: its largest
+                // |c|^2 (wave-uniform)
+                for (int off = 32; off > 0; off >>= 1) {
+                    hmax = fmaxf(hmax, __shfl_xor(hmax, off));
+                    e2max = fmaxf(e2max, __shfl_xor(e2max, off));
+                }
                 const float H = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(hmax)));
-                auto gaps_of = [&](const float4 &qc, float (&gap)[EPT], auto full) {
-                    constexpr bool FULL = decltype(full)::value;  // all EPT slots hold entries
-                    gap[0] = cube_gap(ec[0], qc);  // slot 0 always holds entries
-                    float gmin = gap[0];
-#pragma unroll
-                    for (int j = 1; j < EPT; ++j) {
-                        gap[j] = NAN;
-                        if (FULL || j < nv) {  // wave-uniform: skip slots without entries
-                            gap[j] = cube_gap(ec[j], qc);
-                            gmin = fminf(gmin, gap[j]);
-                        }
-                    }
-                    return gmin;
+                const float E2 = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(e2max)));
+                // s = e2 + (-2C).c with one multiply-add per axis
+                auto dot_of = [&](const float4 &c, const float4 &q) {
+                    return __builtin_fmaf(c.z, q.z, __builtin_fmaf(c.y, q.y, __builtin_fmaf(c.x, q.x, c.w)));
                 };
-                // threshold of a query cube against this chunk: r + H. Its
-                // rounding and that of the distances (at most 2^-23 (r + H)
-                // near the threshold) lie within the 2^-20 slack that r and
-                // every entry half-width carry.
-                auto thr = [&](const float4 &qc) { return qc.w + H; };
-                auto emit = [&](const float t, const int qs, const float (&gap)[EPT]) {
+                // Smallest s of a staged query over the lane's slots.
+                auto gmin_of = [&](const float4 &qv, auto full) {
+                    constexpr bool FULL = decltype(full)::value;
+                    float g = dot_of(ec[0], qv);  // slot 0 always holds entries
 #pragma unroll
-                    for (int j = 0; j < EPT; ++j)
-                        select(gap[j] <= t, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                    for (int j = 1; j < EPT; ++j)
+                        if (FULL || j < nv) g = fminf(g, dot_of(ec[j], qv));
+                    return g;
+                };
+                // The selections of one query: its s are computed again
+                // (this path is rare, and keeping every s of the common path
+                // in registers would cost occupancy).
+                auto emit = [&](const float4 &qv, const int qs, auto full) {
+                    constexpr bool FULL = decltype(full)::value;
+#pragma unroll
+                    for (int j = 0; j < EPT; ++j) {
+                        const bool has = FULL || j < nv;  // wave-uniform
+                        const float g = has ? dot_of(ec[j], qv) : NAN;
+                        select(g <= qv.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                    }
                 };
                 auto count_ovl = [&](const int qs) {
                     if (COUNT_OVL) {
@@ -951,13 +970,17 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         }
                     }
                 };
-                // The wave stages up to 64 query cubes in its LDS slice (one
-                // coalesced load, lane i takes cube s0 + i), then walks them two
-                // at a time with broadcast LDS reads: the gaps of both are
-                // computed before the one (rarely taken) branch, which gives the
-                // scheduler two independent chains. LDS requests of one wave
-                // complete in order, so the slice is rewritten only after the
-                // previous walk has read it.
+                // The wave stages up to 64 query balls in its LDS slice (one
+                // coalesced load, lane i takes ball s0 + i) as (-2C, T), T the
+                // ball's threshold against this chunk, evaluated in binary64
+                // with margins for its own rounding and rounded up:
+                //   T = (r + H)^2 - |C|^2 + kDotSlack (E2 + |C|^2);
+                // then it walks them four at a time with broadcast LDS reads
+                // at fixed offsets: the four smallest s are computed before
+                // the one (rarely taken) branch, which gives the scheduler
+                // four independent chains. LDS requests of one wave complete
+                // in order, so the slice is rewritten only after the previous
+                // walk has read it.
                 __shared__ float4 s_q[BLOCK / 64][kStage];
                 const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
                 auto walk = [&](auto full) {
@@ -965,32 +988,40 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         const int ns = __builtin_amdgcn_readfirstlane(min(kStage, qe - s0));
                         if (lane < ns) {
                             const QCube32 c = box[perm[s0 + lane]];
-                            s_q[wv][lane] = make_float4(c.cx, c.cy, c.cz, c.r);
-                        }
-                        int j = 0;
-                        for (; j + 1 < ns; j += 2) {
-                            const float4 qa = s_q[wv][j], qz = s_q[wv][j + 1];
-                            float ga[EPT], gz[EPT];
-                            const float ma = gaps_of(qa, ga, full), mz = gaps_of(qz, gz, full);
-                            const float ta = thr(qa), tz = thr(qz);
-                            if (__builtin_expect(__ballot(ma <= ta || mz <= tz) != 0ull, 0)) {
-                                emit(ta, s0 + j, ga);
-                                emit(tz, s0 + j + 1, gz);
+                            float4 v = make_float4(0.0f, 0.0f, 0.0f, INFINITY);  // passes all
+                            if (c.r != INFINITY) {
+                                const double C2 = (double)c.cx * c.cx + (double)c.cy * c.cy +
+                                                  (double)c.cz * c.cz;
+                                const double R = (double)c.r + (double)H;
+                                const double T = R * R * (1.0 + 0x1p-40) - C2 * (1.0 - 0x1p-40) +
+                                                 kDotSlack * ((double)E2 + C2);
+                                v = make_float4(-2.0f * c.cx, -2.0f * c.cy, -2.0f * c.cz, f32_up(T));
                             }
-                            count_ovl(s0 + j);
-                            count_ovl(s0 + j + 1);
-                            progress();
-                            progress();
+                            s_q[wv][lane] = v;
                         }
-                        if (j < ns) {
-                            const float4 qa = s_q[wv][j];
-                            float ga[EPT];
-                            const float ma = gaps_of(qa, ga, full);
-                            const float ta = thr(qa);
-                            if (__builtin_expect(__ballot(ma <= ta) != 0ull, 0)) emit(ta, s0 + j, ga);
-                            count_ovl(s0 + j);
-                            progress();
+                        const float4 *sq = s_q[wv];
+                        // kGroup queries per branch (compile-time)
+                        auto group = [&](const int j) {
+                            bool p = false;
+#pragma unroll
+                            for (int k = 0; k < kGroup; ++k) {
+                                const float4 qk = sq[j + k];
+                                p |= gmin_of(qk, full) <= qk.w;
+                            }
+                            if (__builtin_expect(__ballot(p) != 0ull, 0)) {
+                                for (int k = 0; k < kGroup; ++k) emit(sq[j + k], s0 + j + k, full);
+                            }
+                        };
+                        int j = 0;
+                        for (; j + kGroup <= ns; j += kGroup) group(j);
+                        for (; j < ns; ++j) {
+                            const float4 qa = sq[j];
+                            if (__builtin_expect(__ballot(gmin_of(qa, full) <= qa.w) != 0ull, 0))
+                                emit(qa, s0 + j, full);
                         }
+                        if (COUNT_OVL)
+                            for (int k = 0; k < ns; ++k) count_ovl(s0 + k);
+                        progress(ns);
                     }
                 };
                 if (nv == EPT)

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *
     float acc = 0.0f;
     // The chain steps are written as inline assembly (register operands
     // only, no memory access) so that exactly the named instruction is timed.
-    if constexpr (KIND <= 2 || (KIND >= 4 && KIND <= 9)) {
+    if constexpr (KIND <= 2 || (KIND >= 4 && KIND <= 9) || KIND >= 11) {
         float a[kChains];
         float b = seed * 1e-7f + lane * 1e-9f, c = seed * 3e-7f;
 #pragma unroll
@@ -49,6 +49,17 @@ __global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *
                     asm volatile("v_max_f32_e64 %0, |%0|, |%1|" : "+v"(a[k]) : "v"(b));
                 if constexpr (KIND == 8) asm volatile("v_pk_add_f16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
                 if constexpr (KIND == 9) asm volatile("v_min_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 11)
+                    asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+                if constexpr (KIND == 12) asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+                if constexpr (KIND == 13) asm volatile("v_mul_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 14) asm volatile("v_add_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 15) asm volatile("v_or_b32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 16)
+                    asm volatile("v_or3_b32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+                if constexpr (KIND == 17) asm volatile("v_max_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 18)
+                    asm volatile("v_sub_f32_e64 %0, |%0|, %1" : "+v"(a[k]) : "v"(b));
             }
         }
 #pragma unroll
@@ -102,7 +113,9 @@ extern "C" {
  * Runs probe `kind` (0 v_sub_f32, 1 v_max3_f32 with absolute-value operands,
  * 2 v_min3_f32, 3 v_fma_f64, 4 v_add_u32, 5 v_pk_sub_u16, 6 v_pk_max_u16,
  * 7 v_max_f32 with absolute-value operands (VOP3 form), 8 v_pk_add_f16,
- * 9 v_min_f32, 10 v_cmp_le_f32 into a lane mask) with `blocks` workgroups of 256
+ * 9 v_min_f32, 10 v_cmp_le_f32 into a lane mask, 11 v_fma_f32, 12 v_fmac_f32,
+ * 13 v_mul_f32, 14 v_add_f32, 15 v_or_b32, 16 v_or3_b32, 17 v_max_f32,
+ * 18 v_sub_f32 with an absolute-value operand (VOP3 form)) with `blocks` workgroups of 256
  * threads, each lane running `iters` iterations of 8 independent chain
  * steps, on `stream`, and waits for it.
  * Writes: *ms the kernel's duration (HIP events), *wave_instr the vector
@@ -113,7 +126,7 @@ extern "C" {
  */
 int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, double *wave_instr,
                    double *clock_hz) {
-    if (kind < 0 || kind > 10 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
+    if (kind < 0 || kind > 18 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
     hipStream_t s = (hipStream_t)stream;
     const int waves = blocks * (kBlock / 64);
     float *sink = nullptr;
@@ -138,7 +151,15 @@ int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, do
             case 7: err = run_kind<7>(blocks, iters, seed, sink, st, s); break;
             case 8: err = run_kind<8>(blocks, iters, seed, sink, st, s); break;
             case 9: err = run_kind<9>(blocks, iters, seed, sink, st, s); break;
-            default: err = run_kind<10>(blocks, iters, seed, sink, st, s); break;
+            case 10: err = run_kind<10>(blocks, iters, seed, sink, st, s); break;
+            case 11: err = run_kind<11>(blocks, iters, seed, sink, st, s); break;
+            case 12: err = run_kind<12>(blocks, iters, seed, sink, st, s); break;
+            case 13: err = run_kind<13>(blocks, iters, seed, sink, st, s); break;
+            case 14: err = run_kind<14>(blocks, iters, seed, sink, st, s); break;
+            case 15: err = run_kind<15>(blocks, iters, seed, sink, st, s); break;
+            case 16: err = run_kind<16>(blocks, iters, seed, sink, st, s); break;
+            case 17: err = run_kind<17>(blocks, iters, seed, sink, st, s); break;
+            default: err = run_kind<18>(blocks, iters, seed, sink, st, s); break;
             }
         }
         if (err == hipSuccess) err = hipEventRecord(e1, s);

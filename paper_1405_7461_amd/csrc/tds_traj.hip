@@ -5,14 +5,16 @@
 // within d and when (Sec. 3); the segment-pair intervals of one trajectory
 // pair are pieces of that answer, and their union is it. Steps: gather the
 // hits with their two trajectory ids, sort by (query trajectory, entry
-// trajectory, t_a) with three stable radix sorts (least significant key
-// first; merges of up to kTrajOneSortMax hits instead sort whole 32-byte
-// keys once with a comparison merge sort, a third of the launches), then
-// one segmented running maximum of t_b (a single scan whose operator
-// carries the pair-start flag) marks where a new
-// maximal interval starts (its t_a lies after every earlier t_b of the pair;
-// closed intervals that touch merge), and a scan of those marks numbers the
-// output records.
+// trajectory, t_a), then one segmented running maximum of t_b (a single scan
+// whose operator carries the pair-start flag) marks where a new maximal
+// interval starts (its t_a lies after every earlier t_b of the pair; closed
+// intervals that touch merge), and a scan of those marks numbers the output
+// records. The sort: up to kTrajRankMax hits, each key's rank is the number
+// of keys before it (counted by every workgroup of a grid over tiles of
+// keys), a scatter puts them in order and one workgroup does the scans and
+// the records (four launches); up to kTrajOneSortMax hits, one comparison
+// merge sort of whole 32-byte keys; above that, three stable radix sorts
+// (least significant key first).
 #include <hip/hip_runtime.h>
 
 #include <cstring>  // rocprim's headers use memset
@@ -52,6 +54,7 @@ __global__ __launch_bounds__(256) void k_traj_gather(Slabs sl, const Counters *_
             t.tb[k] = h.tb;
             t.key_a[k] = order_bits(h.ta);
             t.idx_a[k] = (int32_t)k;
+            t.start[k] = 0;  // the rank accumulator of small merges
             if (t.kin) t.kin[k] = TrajKey{t.qt[k], t.et[k], h.ta, h.tb};
         }
     }
@@ -142,6 +145,146 @@ struct TrajLess {
     }
 };
 
+// ------------------------------------------------ small merges by ranking
+// Key j precedes key i in the (query trajectory, entry trajectory, t_a)
+// order, ties broken by position, so the ranks of all keys are a
+// permutation.
+__device__ __forceinline__ bool precedes(const TrajKey &kj, long long j, const TrajKey &ki,
+                                         long long i) {
+    if (kj.qt != ki.qt) return kj.qt < ki.qt;
+    if (kj.et != ki.et) return kj.et < ki.et;
+    if (kj.ta != ki.ta) return kj.ta < ki.ta;
+    return j < i;
+}
+
+constexpr int kRankBlock = 256;   // keys i per workgroup (one per thread)
+constexpr int kRankTile = 256;    // keys j per workgroup, staged in LDS
+
+// Grid (i tiles, j tiles): each thread counts the keys of one j tile that
+// precede its key i and adds the count to rank[i] (t.start, zeroed by the
+// gather): n^2 / 64 comparisons per wave spread over the whole GPU.
+__global__ __launch_bounds__(kRankBlock) void k_traj_rank(TrajBufs t, long long n) {
+    __shared__ TrajKey s_k[kRankTile];
+    const long long i = (long long)blockIdx.x * kRankBlock + threadIdx.x;
+    const long long j0 = (long long)blockIdx.y * kRankTile;
+    const int nj = (int)min((long long)kRankTile, n - j0);
+    for (int k = threadIdx.x; k < nj; k += kRankBlock) s_k[k] = t.kin[j0 + k];
+    __syncthreads();
+    if (i >= n) return;
+    const TrajKey ki = t.kin[i];
+    int c = 0;
+    for (int k = 0; k < nj; ++k) c += precedes(s_k[k], j0 + k, ki, i) ? 1 : 0;
+    if (c) atomicAdd(&t.start[i], c);
+}
+
+// Sorted order: kout[rank[i]] = kin[i].
+__global__ void k_traj_scatter(TrajBufs t, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) t.kout[t.start[i]] = t.kin[i];
+}
+
+constexpr int kMergeBlock = 1024;
+constexpr int kMergeItems = (int)(kTrajRankMax / kMergeBlock);  // items per thread
+
+// Inclusive scan of one value per thread over the workgroup (Hillis-Steele in
+// LDS, s holds kMergeBlock values); afterwards s[k] is thread k's inclusive
+// value.
+template <class T, class Op>
+__device__ __forceinline__ T block_scan_incl(T v, Op op, T *s) {
+    const int tid = threadIdx.x;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kMergeBlock; off <<= 1) {
+        const T o = tid >= off ? s[tid - off] : v;
+        __syncthreads();
+        if (tid >= off) v = op(o, v);
+        s[tid] = v;
+        __syncthreads();
+    }
+    return v;
+}
+
+struct IntPlus {
+    __device__ int operator()(int a, int b) const { return a + b; }
+};
+
+// One workgroup over the sorted keys (n <= kTrajRankMax, consecutive items
+// per thread): pair-start flags, the running maximum of t_b within each pair
+// (segmented scan), the starts of maximal intervals (t_a beyond every earlier
+// t_b of the pair), their record numbers (scan), and the records.
+__global__ __launch_bounds__(kMergeBlock) void k_traj_merge_one(TrajBufs t, long long n,
+                                                                tds_traj_hit *__restrict__ out,
+                                                                long long *__restrict__ total) {
+    __shared__ SegMax s_seg[kMergeBlock];
+    __shared__ int s_cnt[kMergeBlock];
+    const int tid = threadIdx.x;
+    const long long b0 = (long long)tid * kMergeItems;
+    TrajKey k[kMergeItems];
+    bool f[kMergeItems];
+    // pair-start flags and the thread's own segmented maximum
+    SegMax agg{-INFINITY, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kMergeItems; ++j) {
+        const long long i = b0 + j;
+        f[j] = false;
+        if (i < n) {
+            k[j] = t.kout[i];
+            bool st = i == 0;
+            if (!st) {
+                const TrajKey p = j ? k[j - 1] : t.kout[i - 1];
+                st = k[j].qt != p.qt || k[j].et != p.et;
+            }
+            f[j] = st;
+            agg = SegMaxOp()(agg, SegMax{k[j].tb, st ? 1 : 0, 0});
+        }
+    }
+    block_scan_incl(agg, SegMaxOp(), s_seg);
+    // the segmented maximum over the earlier threads' items
+    SegMax run = tid ? s_seg[tid - 1] : SegMax{-INFINITY, 0, 0};
+    // starts of maximal intervals and the running maxima
+    int cnt = 0;
+    bool st[kMergeItems];
+    double runmax[kMergeItems];
+#pragma unroll
+    for (int j = 0; j < kMergeItems; ++j) {
+        const long long i = b0 + j;
+        st[j] = false;
+        runmax[j] = 0.0;
+        if (i < n) {
+            st[j] = f[j] || k[j].ta > run.v;
+            run = SegMaxOp()(run, SegMax{k[j].tb, f[j] ? 1 : 0, 0});
+            runmax[j] = run.v;
+            cnt += st[j] ? 1 : 0;
+        }
+    }
+    const int cinc = block_scan_incl(cnt, IntPlus(), s_cnt);
+    long long m = (long long)(cinc - cnt) - 1;  // record of the last start before these items
+#pragma unroll
+    for (int j = 0; j < kMergeItems; ++j) {
+        const long long i = b0 + j;
+        if (i < n) {
+            if (st[j]) {
+                ++m;
+                out[m].query_traj = k[j].qt;
+                out[m].entry_traj = k[j].et;
+                out[m].t_a = k[j].ta;
+            }
+            // the last item of a run gives its t_b: the next item starts a run
+            bool last = i == n - 1;
+            if (!last) {
+                if (j + 1 < kMergeItems) {
+                    last = st[j + 1];
+                } else {
+                    const TrajKey nx = t.kout[i + 1];
+                    last = nx.qt != k[j].qt || nx.et != k[j].et || nx.ta > runmax[j];
+                }
+            }
+            if (last) out[m].t_b = runmax[j];
+            if (i == n - 1) *total = m + 1;
+        }
+    }
+}
+
 // Merge sort of the small merges: block sort of SortBlock x SortItems keys,
 // then merge passes. Measured on 7,940 hits: 512 keys per block 0.149-0.155
 // ms per merge, 1,024 0.17-0.18, rocprim's default for 32-byte keys 0.195
@@ -216,6 +359,13 @@ hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const i
     if (one && (!t.kin || !t.kout)) return hipErrorInvalidValue;
     if (!one) t.kin = t.kout = nullptr;
     hipLaunchKernelGGL(k_traj_gather, dim3(1024), dim3(256), 0, st, sl, ctr, perm, qtraj, ix, t);
+    if (n <= kTrajRankMax) {
+        const dim3 rg((unsigned)((n + kRankBlock - 1) / kRankBlock), (unsigned)((n + kRankTile - 1) / kRankTile));
+        hipLaunchKernelGGL(k_traj_rank, rg, dim3(kRankBlock), 0, st, t, n);
+        hipLaunchKernelGGL(k_traj_scatter, dim3(g), dim3(blk), 0, st, t, n);
+        hipLaunchKernelGGL(k_traj_merge_one, dim3(1), dim3(kMergeBlock), 0, st, t, n, out, total);
+        return hipGetLastError();
+    }
     hipError_t e;
     size_t b = temp_bytes;
     if (one) {

@@ -205,3 +205,16 @@ def test_hit_dense_full_size():
 class TrajHitsView:
     def __init__(self, qt, et, ta, tb):
         self.query_traj, self.entry_traj, self.ta, self.tb = qt, et, ta, tb
+
+
+@pytest.mark.parametrize("nq,d", [(40, 1.5), (40, 2.5)])
+def test_small_and_large_merge_paths(nq, d):
+    """Up to 8,192 segment hits are merged by ranking each key by counting and
+    one workgroup's segmented scan; more go through the radix sorts. Both are
+    checked against the oracle's union (about 5,100 and 16,500 hits here)."""
+    db, q = fx.dense_box(ntraj=60, L=20, box=4.0, nq=nq, seed=43, d=d)
+    want, h = _oracle_union(db, q)
+    say(f"merge paths: {len(h)} segment hits -> {len(want)} trajectory intervals")
+    for mode in MODES:
+        u = _device_union(db, q, 20, mode)
+        _compare(u, want, f"dense nq={nq} d={d} {mode}")
