@@ -125,26 +125,37 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
     stream = torch.cuda.current_stream()
     # one untimed pass that also counts overlapping pairs (checked against N_ovl)
     qh.batch(dq, dq.d, count_overlap=True, stream=stream, **opts)
-    qh.fetch(out="device")
+    counted_hits = len(qh.fetch(out="device"))
     counted = qh.stats()["n_overlap"]
     lat, pair_ms, stats = [], [], None
-    # the device arrays are marshalled once, as a C caller holds its pointers
+    # A step as a C caller runs it: the device arrays, the options and the
+    # output buffer are set up once; each step is tds_query_batch, then
+    # tds_fetch_results into device memory, then a wait on the batch's stream
+    # (the records are written on it). HIP events on the pair kernel's
+    # dispatch (the lightest timing) are read after the step.
+    import ctypes as C
+    from paper_1405_7461_amd import _lib as L
+    lib = L.lib()
     prep = tds.prepare(dq, dq.d)
+    o = tds.api.query_opts(timing="pair", **opts)
+    cap = max(1024, 2 * counted_hits)
+    out = torch.empty((cap, 5), dtype=torch.int64, device="cuda")
+    optr, sh, nh = C.c_void_p(out.data_ptr()), stream.cuda_stream, C.c_int64()
+    seg, dptr = C.byref(prep.segments), prep.dptr
     for i in range(warmup + steps):
-        torch.cuda.synchronize()
+        stream.synchronize()
         t0 = time.perf_counter()
-        # HIP events on the pair kernel's dispatch (the lightest timing); the
-        # event times are read after the step
-        qh.batch(prep, None, timing="pair", stream=stream, **opts)
-        h = qh.fetch(out="device")
-        torch.cuda.synchronize()
+        rc = lib.tds_query_batch(qh.handle, seg, dptr, C.byref(o), sh)
+        rc = rc or lib.tds_fetch_results(qh.handle, optr, cap, L.TDS_MEM_DEVICE, C.byref(nh))
+        stream.synchronize()
         t1 = time.perf_counter()
+        L.check(rc)
         if i >= warmup:
             st = qh.stats()
             lat.append(t1 - t0)
             pair_ms.append(st["ms_pair"])
             stats = st
-            n_hit = len(h)
+            n_hit = int(nh.value)
     # stage breakdown from a few more steps with every stage timed
     prep_ms, refine_ms = [], []
     for i in range(3):
@@ -390,7 +401,7 @@ def model_form(log_fn=log, steps=8, warmup=2):
     return out
 
 
-def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4):
+def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4, max_batch=65536):
     """C5: 10M-segment resident index; requests served by the library's
     native scheduler (tds_server_*: admission by estimated result bytes,
     continuous batching over `streams` HIP streams, per-request split in
@@ -417,7 +428,7 @@ def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4)
            f"{n_ovl.sum():.4g} overlapping pairs) generated in {gen_s:.1f} s")
 
     def serve(arrivals, warm=False):
-        srv = tds.NativeServer(ix, streams=streams, max_batch_segments=65536,
+        srv = tds.NativeServer(ix, streams=streams, max_batch_segments=max_batch,
                                mode="fp32_refine", tiling="range")
         if warm:  # first batches of a fresh server: untimed
             ids = [srv.submit(q, q.d, 0.0) for q in reqs[:256]]
@@ -472,7 +483,8 @@ def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4)
     return dict(workload="C5: 10M-segment Gaussian walk (25,000 x 400) resident; requests of log-uniform "
                          "length 10-5000 (segments of 1/16), d log-uniform in [0.5, 50]; Poisson arrivals",
                 engine="native scheduler (tds_server_*), fp32_refine, range tiles",
-                streams=streams, n_requests=n_requests, build_s=round(build_s, 2),
+                streams=streams, max_batch_segments=max_batch, n_requests=n_requests,
+                build_s=round(build_s, 2),
                 saturation_req_s=sat_rate, saturation_pair_tests_s=float(n_ovl.sum() / sat["wall_s"]),
                 saturation_p50_ms=sat["p50_ms"], saturation_batches=sat["batches"],
                 saturation_busy_s=sat["busy_s"], device_bytes=sat["device_bytes"],

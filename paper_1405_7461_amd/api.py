@@ -214,6 +214,16 @@ def prepare(q, d) -> Prepared:
     return Prepared(q, d)
 
 
+def query_opts(mode="fp64", tiling="periodic", batch_size=0, block_size=0, capacity=0, grid=0,
+               max_retries=-1, timing=False, count_overlap=False, kernel_overlap=False):
+    """tds_query_opts; timing: True records every stage, "pair" only the pair kernel."""
+    tflag = L.TDS_QF_TIMING_PAIR if timing == "pair" else (L.TDS_QF_TIMING if timing else 0)
+    flags = (tflag | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
+             | (L.TDS_QF_KERNEL_OVERLAP if kernel_overlap else 0))
+    return L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,
+                            int(max_retries), int(capacity), int(grid), flags)
+
+
 class Query:
     """One query handle (tds_query_create): buffers reused across batches."""
 
@@ -227,17 +237,18 @@ class Query:
         self._stream = None
         self._rows_hint = 1024  # output rows for the next fetch
 
+    @property
+    def handle(self):
+        """The tds_query pointer (for callers of the C ABI)."""
+        return self._h
+
     def batch(self, q, d, mode="fp64", tiling="periodic", batch_size=0, block_size=0,
               capacity=0, grid=0, max_retries=-1, timing=False, count_overlap=False,
               kernel_overlap=False, stream=None):
         p = q if isinstance(q, Prepared) else Prepared(q, d)
         s, dptr, keep = p.segments, p.dptr, p.keep
-        # timing: True records every stage, "pair" only the pair kernel
-        tflag = L.TDS_QF_TIMING_PAIR if timing == "pair" else (L.TDS_QF_TIMING if timing else 0)
-        flags = (tflag | (L.TDS_QF_COUNT_OVERLAP if count_overlap else 0)
-                 | (L.TDS_QF_KERNEL_OVERLAP if kernel_overlap else 0))
-        o = L.tds_query_opts(MODES[mode], TILINGS[tiling], int(batch_size), int(block_size), 0,
-                             int(max_retries), int(capacity), int(grid), flags)
+        o = query_opts(mode, tiling, batch_size, block_size, capacity, grid, max_retries, timing,
+                       count_overlap, kernel_overlap)
         L.check(L.lib().tds_query_batch(self._h, C.byref(s), dptr, C.byref(o), _stream_handle(stream)))
         self._stream = stream
         self._keep = keep  # device inputs must outlive the batch

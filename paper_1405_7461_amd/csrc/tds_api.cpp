@@ -192,6 +192,13 @@ struct tds_query {
     long long nslabs_alloc = 0;    // slabs the cand / hits buffers hold
     int32_t nwaves_alloc = 0;      // wave slabs slab_n / wave_ovl hold
     Counters *host_ctr = nullptr;  // pinned
+    // The batch counters live in two slots used in turn: the hit scan of a
+    // batch clears the other slot and the bucket counters, so the next batch
+    // starts without a clearing kernel. clear_needed: they were not cleared
+    // (new buffers, a batch without segments, an error).
+    int ctr_slot = 0;
+    bool clear_needed = true;
+    NextClear next{};
     hipStream_t stream = nullptr;
     DevBatch b{};
     tds_query_opts opts{};
@@ -545,12 +552,13 @@ int tds_query_create(tds_index *ix, tds_query **out) {
     if (!ix || !out) return fail(TDS_EINVAL, "tds_query_create: null argument");
     tds_query *q = new tds_query();
     q->ix = ix;
-    hipError_t e = hipHostMalloc((void **)&q->host_ctr, sizeof(Counters), hipHostMallocDefault);
+    // pinned: the final counters, then the trajectory merge's record count
+    hipError_t e = hipHostMalloc((void **)&q->host_ctr, sizeof(Counters) + 64, hipHostMallocDefault);
     if (e != hipSuccess) {
         delete q;
         return fail(TDS_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
-    std::memset(q->host_ctr, 0, sizeof(Counters));
+    std::memset(q->host_ctr, 0, sizeof(Counters) + 64);
     for (auto &ev : q->ev) {
         e = hipEventCreate(&ev);
         if (e != hipSuccess) {
@@ -594,14 +602,16 @@ static int ensure_capacity(tds_query *q, int32_t nq, int32_t nbuckets) {
         HIP_TRY(q->units.ensure(n1 * 8));
         HIP_TRY(q->unit_off.ensure(n1 * 8));
         HIP_TRY(q->cost_off.ensure(n1 * 8));
-        HIP_TRY(q->ctr.ensure(sizeof(Counters)));
+        HIP_TRY(q->ctr.ensure(2 * sizeof(Counters)));
         q->cap_q = c;
+        q->clear_needed = true;
     }
     if (nbuckets > q->cap_buckets) {
         size_t n = (size_t)nbuckets;
         for (DBuf *b : {&q->bcount, &q->bq_off}) HIP_TRY(b->ensure(n * kBucketSub * 4));
         HIP_TRY(q->bj2.ensure(n * 4));
         q->cap_buckets = nbuckets;
+        q->clear_needed = true;
     }
     return TDS_OK;
 }
@@ -709,7 +719,7 @@ static int launch_search(tds_query *q) {
     // the scan kernel writes the final counters to host_ctr itself; a batch
     // without query segments launches no scan, so its counters are copied
     HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream, timing ? q->ev[3] : nullptr,
-                          q->host_ctr));
+                          q->host_ctr, q->next));
     if (q->b.nq == 0)
         HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
                                q->stream));
@@ -772,10 +782,10 @@ static void batch_scalars(DevBatch &b, const tds_query_opts &o, int32_t nq, int 
 // tds_query_batch and tds_search_noalloc).
 static int enqueue_tiles(DevBatch &b, const GreedyBufs &gb, const tds_index *ix,
                          const double *const *qin, const double *din, const tds_query_opts &o,
-                         hipStream_t st, hipEvent_t ev_start) {
+                         hipStream_t st, hipEvent_t ev_start, bool zero = true) {
     const bool greedy = o.tiling == TDS_TILE_GREEDY_MIN || o.tiling == TDS_TILE_GREEDY_MAX;
     const bool sorted = greedy || o.tiling == TDS_TILE_PERIODIC;
-    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st, ev_start));
+    HIP_TRY(launch_prepare(qin, din, b, ix->dev, st, ev_start, zero));
     if (sorted && b.nq > 0) HIP_TRY(launch_bucket_sort(b, st));
     if (o.tiling == TDS_TILE_PERIODIC && b.nq > 0) HIP_TRY(launch_periodic(b, ix->dev, st));
     if (greedy && b.nq > 0)
@@ -847,7 +857,10 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.units = q->units.as<long long>();
     b.unit_off = q->unit_off.as<long long>();
     b.cost_off = q->cost_off.as<long long>();
-    b.ctr = q->ctr.as<Counters>();
+    b.ctr = q->ctr.as<Counters>() + q->ctr_slot;
+    // the hit scan of this batch clears the next batch's counters
+    q->next = NextClear{q->ctr.as<Counters>() + (q->ctr_slot ^ 1), q->bcount.as<int32_t>(),
+                        q->bj2.as<int32_t>(), q->cap_buckets, 0};
 
     // Periodic and the greedy tilings walk the segments in exact
     // (t_start, caller index) order, sorted within each t_start bin
@@ -866,10 +879,15 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     }
 
     const bool timing = (o.flags & TDS_QF_TIMING) != 0;
-    rc = enqueue_tiles(b, gb, ix, qin, din, o, st, timing ? q->ev[0] : nullptr);
+    const bool zero = q->clear_needed;
+    q->clear_needed = true;  // until the whole batch is enqueued
+    rc = enqueue_tiles(b, gb, ix, qin, din, o, st, timing ? q->ev[0] : nullptr, zero);
     if (rc) return rc;
     rc = launch_search(q);
     if (rc) return rc;
+    // a batch without segments launches no hit scan, which would clear
+    q->clear_needed = nq == 0;
+    q->ctr_slot ^= 1;
     q->pending = true;
     q->fetched = false;
     q->traj_valid = false;
@@ -934,6 +952,7 @@ static int complete_batch(tds_query *q, const char *who) {
         Counters c = *q->host_ctr;
         if (c.err) {
             q->pending = false;
+            q->clear_needed = true;
             return fail(TDS_EINVAL, "%s: the batch holds an invalid query "
                                     "segment (non-finite value, t_end <= t_start, or d < 0)", who);
         }
@@ -943,6 +962,7 @@ static int complete_batch(tds_query *q, const char *who) {
         while (c.spill > spill_capacity(q->sl)) {
             if (retries >= q->opts.max_retries) {
                 q->pending = false;
+                q->clear_needed = true;
                 return fail(TDS_EOVERFLOW,
                             "%s: the selections needed %llu spill slabs of %d records "
                             "beyond the wave slabs; capacity %llu",
@@ -951,11 +971,13 @@ static int complete_batch(tds_query *q, const char *who) {
             ++retries;
             // the count is exact (a wave's slabs depend only on its own
             // selections), so this size suffices for the re-run
+            q->clear_needed = true;  // until the re-run is enqueued
             int rc = ensure_slabs(q, q->sl.nwaves, c.spill);
             if (rc) return rc;
             HIP_TRY(launch_reset_counters(q->b.ctr, 1, st));
             rc = launch_search(q);
             if (rc) return rc;
+            q->clear_needed = false;
             HIP_TRY(hipStreamSynchronize(st));
             c = *q->host_ctr;
         }
@@ -1111,18 +1133,21 @@ int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj
     take8((void *&)t.key_a); take8((void *&)t.key_b); take8((void *&)t.sta);
     take4((void *&)t.idx_a); take4((void *&)t.idx_b); take4((void *&)t.flag);
     take4((void *&)t.start); take4((void *&)t.mid);
-    const size_t temp = traj_temp_bytes(n);
-    if (temp == 0) return fail(TDS_EDEVICE, "tds_fetch_trajectories: sort sizing failed");
-    HIP_TRY(q->tr_temp.ensure(temp));
+    // the library sorts (all but the smallest merges) need temporary storage
+    const size_t temp = n <= kTrajRankMax ? 0 : traj_temp_bytes(n);
+    if (n > kTrajRankMax && temp == 0)
+        return fail(TDS_EDEVICE, "tds_fetch_trajectories: sort sizing failed");
+    if (temp) HIP_TRY(q->tr_temp.ensure(temp));
     HIP_TRY(q->tr_out.ensure(nn * sizeof(tds_traj_hit) + sizeof(long long)));
     tds_traj_hit *recs = q->tr_out.as<tds_traj_hit>();
     long long *total_dev = reinterpret_cast<long long *>(recs + nn);
     HIP_TRY(launch_traj_merge(q->sl, q->b.ctr, n, q->b.perm, qt, q->ix->dev, t, q->tr_temp.p,
                               q->tr_temp.bytes, recs, total_dev, st));
-    long long total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, total_dev, sizeof total, hipMemcpyDeviceToHost, st));
+    // the record count to pinned host memory (after the handle's counters)
+    long long *host_total = reinterpret_cast<long long *>(reinterpret_cast<char *>(q->host_ctr) + sizeof(Counters));
+    HIP_TRY(hipMemcpyAsync(host_total, total_dev, sizeof(long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    q->traj_total = total;
+    q->traj_total = *host_total;
     q->traj_valid = true;
     return copy_traj(q, out, cap, out_mem, n_total);
 }

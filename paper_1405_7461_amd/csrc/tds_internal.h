@@ -370,9 +370,21 @@ hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *per
                          double *z0, double *vx, double *vy, double *vz, float4 *ecen,
                          float *erad, double ox, double oy, double oz, int32_t *orig,
                          int64_t *traj, hipStream_t st);
-// ev_start (optional) records the start of the first kernel.
+// ev_start (optional) records the start of the first kernel. With zero
+// false the per-bucket counters and the batch counters are taken as already
+// cleared (the previous batch's hit scan cleared them, see NextClear).
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
-                          hipStream_t st, hipEvent_t ev_start = nullptr);
+                          hipStream_t st, hipEvent_t ev_start = nullptr, bool zero = true);
+// What the last kernel of a batch clears for the next batch of the same
+// query handle (null ctr: nothing): the next batch's counters and the first
+// nbuckets per-bucket counters (bcount = 0, bj2 = -1).
+struct NextClear {
+    Counters *ctr;
+    int32_t *bcount;
+    int32_t *bj2;
+    int32_t nbuckets;
+    int32_t pad;
+};
 // Workgroups of the pair launch: `grid` when > 0, else one per resident slot
 // (persistent launch). Slabs.nwaves must be pair_grid(...) * block / 64.
 int pair_grid(int mode, int block, int grid, int kernel_overlap);
@@ -383,7 +395,8 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
 // ev_stop (optional) records the end of the scan.
 // host_out (optional): pinned host copy of the final counters, written by the scan.
 hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
-                         hipEvent_t ev_stop = nullptr, Counters *host_out = nullptr);
+                         hipEvent_t ev_stop = nullptr, Counters *host_out = nullptr,
+                         NextClear next = NextClear{});
 // Dense caller-index records of the first n hits.
 hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
                             DevIndex ix, void *out_hits, hipStream_t st);

@@ -618,16 +618,19 @@ __global__ __launch_bounds__(kScanBlock) void k_unit_scan(DevBatch b) {
 }
 
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
-                          hipStream_t st, hipEvent_t ev_start) {
+                          hipStream_t st, hipEvent_t ev_start, bool zero) {
     const int blk = 256;
-    int zgrid = (b.nbuckets + blk - 1) / blk;
-    zgrid = zgrid < 1 ? 1 : (zgrid > 1024 ? 1024 : zgrid);
-    TDS_LAUNCH_EV(ev_start, nullptr, k_zero_batch, dim3(zgrid), dim3(blk), 0, st, b);
+    if (zero || b.nq == 0) {
+        int zgrid = (b.nbuckets + blk - 1) / blk;
+        zgrid = zgrid < 1 ? 1 : (zgrid > 1024 ? 1024 : zgrid);
+        TDS_LAUNCH_EV(ev_start, nullptr, k_zero_batch, dim3(zgrid), dim3(blk), 0, st, b);
+        ev_start = nullptr;
+    }
     if (b.nq == 0) TDS_LAUNCH_CHECK();
     const int qgrid = (b.nq + blk - 1) / blk;
     const size_t lds = ix.nb <= kQprepLdsBins ? (size_t)ix.nb * 2 * sizeof(double) : 0;
-    hipLaunchKernelGGL(k_qprep, dim3(qgrid), dim3(blk), lds, st, q[0], q[1], q[2], q[3], q[4], q[5],
-                       q[6], q[7], d, b, ix);
+    TDS_LAUNCH_EV(ev_start, nullptr, k_qprep, dim3(qgrid), dim3(blk), lds, st, q[0], q[1], q[2], q[3],
+                  q[4], q[5], q[6], q[7], d, b, ix);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanBlock), 0, st, b, ix);
     hipLaunchKernelGGL(k_scatter, dim3(qgrid), dim3(blk), 0, st, b);
     TDS_LAUNCH_CHECK();
@@ -1107,7 +1110,17 @@ constexpr int kScanRun = 8;
 // The final counters also go to `host_out` (pinned host memory that the host
 // reads after the stream is synchronized), which saves a copy on the stream.
 __global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
-                                                         int count_ovl, Counters *host_out) {
+                                                         int count_ovl, Counters *host_out,
+                                                         NextClear next) {
+    // the next batch of this handle starts from cleared counters (its own
+    // Counters slot, and bucket counters no kernel of this batch reads now)
+    if (next.ctr) {
+        for (int k = threadIdx.x; k < next.nbuckets; k += kScanBlock) {
+            next.bcount[k] = 0;
+            next.bj2[k] = -1;
+        }
+        if (threadIdx.x == 0) *next.ctr = Counters{};
+    }
     const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
     const long long per = (nsl + kScanBlock - 1) / kScanBlock;
     const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
@@ -1273,7 +1286,7 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
 }
 
 hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
-                         hipEvent_t ev_stop, Counters *host_out) {
+                         hipEvent_t ev_stop, Counters *host_out, NextClear next) {
     if (b.nq == 0) {
         if (ev_stop) (void)hipEventRecord(ev_stop, st);
         return hipGetLastError();
@@ -1281,7 +1294,7 @@ hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipSt
     static const int grid = resident_blocks(k_refine, 256);
     hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix, b.ctr);
     TDS_LAUNCH_EV(nullptr, ev_stop, k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr,
-                  count_ovl, host_out);
+                  count_ovl, host_out, next);
     TDS_LAUNCH_CHECK();
 }
 

@@ -397,3 +397,45 @@ def test_outlier_band_stays_local():
     say(f"outlier: refined {st1['n_refine']} -> {st2['n_refine']} ({n_step} query segments at its step)")
     assert st2["n_refine"] - st1["n_refine"] <= 256 * n_step
     assert st2["n_refine"] < st1["n_refine"] + 0.05 * st2["n_eval"]
+
+
+def test_handle_reuse_across_batches():
+    """One query handle runs batches of several tilings, sizes and modes in a
+    row (each batch starts from the counters the previous batch's last
+    kernel cleared, or from a clearing kernel after a buffer grew, an empty
+    batch or an invalid one); every batch equals the oracle."""
+    db = gen.make_db("C4", ntraj=300)
+    qa = gen.make_queries("C4", nq=12)
+    qb = gen.make_queries("C4", nq=40)
+    want_a, want_b = oracle.search(db, qa), oracle.search(db, qb)
+    ix = tds.build_index(db, 800)
+    qh = tds.Query(ix)
+    import torch
+    empty = qa.subset(np.arange(0))
+    # device segments are checked by the preparation kernel: an invalid one
+    # fails the batch at fetch time, after its kernels ran
+    bad = qa.subset(np.arange(4))
+    bad.t1 = bad.t0.copy()  # t_end == t_start: invalid
+    for f in ("x0", "y0", "z0", "t0", "x1", "y1", "z1", "t1"):
+        setattr(bad, f, torch.as_tensor(getattr(bad, f), device="cuda"))
+    seq = [("a", "range", "fp32_refine"), ("a", "range", "fp32_refine"), ("b", "periodic", "fp64"),
+           ("a", "greedy_min", "fp32_refine"), ("empty", "range", "fp64"), ("b", "greedy_max", "fp32_refine"),
+           ("bad", "range", "fp32_refine"), ("a", "range", "fp64"), ("b", "range", "fp32_refine"),
+           ("a", "periodic", "fp32_refine")]
+    try:
+        for k, (which, tiling, mode) in enumerate(seq):
+            q = {"a": qa, "b": qb, "empty": empty, "bad": bad}[which]
+            d = q.d if which != "bad" else torch.ones(4, dtype=torch.float64, device="cuda")
+            qh.batch(q, d, mode=mode, tiling=tiling, batch_size=64)
+            if which == "bad":
+                with pytest.raises(tds.TdsError):
+                    qh.fetch()
+                continue
+            got = qh.fetch().sorted()
+            if which == "empty":
+                assert len(got) == 0
+                continue
+            compare(got, want_a if which == "a" else want_b, db, f"batch {k}: {which} {tiling} {mode}")
+    finally:
+        qh.close()
+        ix.close()
