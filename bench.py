@@ -239,30 +239,42 @@ def trajectory_form(ix, db, dq, q, opts, log_fn=log, steps=10, warmup=2):
     cases = [("C2 headline batch (120,000 query segments, ids per trajectory and d)", dq, head_ids),
              ("hit-dense: the 2,500 database trajectories shifted by 0.5 in x, d = 5 "
               "(1,000,000 query segments)", to_device(shifted), shifted.traj)]
+    import ctypes as C
+    from paper_1405_7461_amd import _lib as L
+    lib = L.lib()
     out = []
     for label, qdev, ids in cases:
         qh = tds.Query(ix)
         prep = tds.prepare(qdev, qdev.d)
         ids_dev = torch.as_tensor(ids, device="cuda")
+        # sizes from one untimed pass; then, as a C caller with a buffer of
+        # that size, one call merges and copies the records
+        qh.batch(prep, None, stream=stream, **opts)
+        n_hit = len(qh.fetch(out="device"))
+        n_out = len(qh.fetch_trajectories(ids_dev, out="device"))
+        rec = torch.empty((max(n_out, 1), 4), dtype=torch.int64, device="cuda")
+        nn = C.c_int64()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         wall, gpu, seg_ms = [], [], []
         for i in range(warmup + steps):
-            torch.cuda.synchronize()
+            stream.synchronize()
             t0 = time.perf_counter()
             qh.batch(prep, None, stream=stream, **opts)
             h = qh.fetch(out="device")
-            torch.cuda.synchronize()
+            stream.synchronize()
             t1 = time.perf_counter()
             ev0.record(stream)
-            u = qh.fetch_trajectories(ids_dev, out="device")
+            L.check(lib.tds_fetch_trajectories(qh.handle, C.c_void_p(ids_dev.data_ptr()), L.TDS_MEM_DEVICE,
+                                               C.c_void_p(rec.data_ptr()), rec.shape[0], L.TDS_MEM_DEVICE,
+                                               C.byref(nn)))
             ev1.record(stream)
-            torch.cuda.synchronize()
+            stream.synchronize()
             t2 = time.perf_counter()
             if i >= warmup:
                 seg_ms.append((t1 - t0) * 1e3)
                 wall.append((t2 - t1) * 1e3)
                 gpu.append(ev0.elapsed_time(ev1))
-        n_hit, n_out = len(h), len(u)
+        assert len(h) == n_hit and nn.value == n_out
         st = qh.stats()
         qh.close()
         merge_ms = float(np.mean(gpu))
@@ -401,7 +413,7 @@ def model_form(log_fn=log, steps=8, warmup=2):
     return out
 
 
-def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4, max_batch=65536):
+def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4, max_batch=16384):
     """C5: 10M-segment resident index; requests served by the library's
     native scheduler (tds_server_*: admission by estimated result bytes,
     continuous batching over `streams` HIP streams, per-request split in

@@ -14,9 +14,12 @@ Result bytes are estimated as in the paper's performance model (Sec. 8):
 the hit fraction alpha is tracked per temporal epoch (50 epochs over the
 database's time extent), and a query segment's expected hits are alpha of
 its epoch times its number of candidate entries (computed on the host from
-the bin table). The estimates are updated from every completed batch. A
-batch whose estimate is too small still completes: the library re-runs the
-pair kernel with a larger buffer.
+the bin table). Alpha is updated from every completed batch, and a waiting
+request is estimated again each time a batch is formed. A batch whose
+estimate is too small still completes: the library re-runs the pair kernel
+with a larger buffer. The library's native scheduler (tds_server_*, the
+NativeServer binding) follows the same policy; this one keeps it in Python
+for host tests with the oracle standing in for the GPU.
 """
 from __future__ import annotations
 
@@ -143,6 +146,10 @@ class Server:
         else:
             r._n_eval_seg = np.zeros(r.n)
         r.n_eval = int(r._n_eval_seg.sum())
+        self.estimate(r)
+
+    def estimate(self, r: Request):
+        """Estimated result bytes of a planned request under the current alpha."""
         r.est_bytes = HIT_BYTES * self.k_safety * max(1.0, self.alpha.expected_hits(r.seg.t0, r._n_eval_seg))
 
     # -------------------------------------------------------------- running
@@ -267,6 +274,9 @@ class Server:
                         budget = self.pool_bytes - self.in_flight_bytes
                         while pending:
                             r = pending[0]
+                            # waiting requests are re-estimated with the alpha
+                            # the batches completed so far have updated
+                            self.estimate(r)
                             fits = (nbytes + r.est_bytes <= budget or not batch and self.in_flight_bytes == 0)
                             if not fits or (batch and nseg + r.n > self.max_batch_segments):
                                 break
