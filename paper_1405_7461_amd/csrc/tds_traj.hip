@@ -146,34 +146,42 @@ struct TrajLess {
 };
 
 // ------------------------------------------------ small merges by ranking
-// Key j precedes key i in the (query trajectory, entry trajectory, t_a)
-// order, ties broken by position, so the ranks of all keys are a
-// permutation.
-__device__ __forceinline__ bool precedes(const TrajKey &kj, long long j, const TrajKey &ki,
-                                         long long i) {
-    if (kj.qt != ki.qt) return kj.qt < ki.qt;
-    if (kj.et != ki.et) return kj.et < ki.et;
-    if (kj.ta != ki.ta) return kj.ta < ki.ta;
-    return j < i;
-}
-
 constexpr int kRankBlock = 256;   // keys i per workgroup (one per thread)
 constexpr int kRankTile = 256;    // keys j per workgroup, staged in LDS
 
 // Grid (i tiles, j tiles): each thread counts the keys of one j tile that
-// precede its key i and adds the count to rank[i] (t.start, zeroed by the
-// gather): n^2 / 64 comparisons per wave spread over the whole GPU.
+// precede its key i in the (query trajectory, entry trajectory, t_a) order,
+// ties broken by position so that the ranks are a permutation, and adds the
+// count to rank[i] (t.start, zeroed by the gather). The comparison is
+// evaluated without branches (lane masks combined), the j keys are
+// broadcast from LDS as three arrays and the loop is unrolled so that their
+// reads overlap: n^2 / 64 comparisons per wave spread over the whole GPU.
 __global__ __launch_bounds__(kRankBlock) void k_traj_rank(TrajBufs t, long long n) {
-    __shared__ TrajKey s_k[kRankTile];
+    __shared__ long long s_q[kRankTile], s_e[kRankTile];
+    __shared__ double s_t[kRankTile];
     const long long i = (long long)blockIdx.x * kRankBlock + threadIdx.x;
     const long long j0 = (long long)blockIdx.y * kRankTile;
     const int nj = (int)min((long long)kRankTile, n - j0);
-    for (int k = threadIdx.x; k < nj; k += kRankBlock) s_k[k] = t.kin[j0 + k];
+    for (int k = threadIdx.x; k < nj; k += kRankBlock) {
+        const TrajKey kk = t.kin[j0 + k];
+        s_q[k] = kk.qt;
+        s_e[k] = kk.et;
+        s_t[k] = kk.ta;
+    }
     __syncthreads();
     if (i >= n) return;
     const TrajKey ki = t.kin[i];
+    const long long lim = i - j0;  // tile slots k < lim hold keys at earlier positions
     int c = 0;
-    for (int k = 0; k < nj; ++k) c += precedes(s_k[k], j0 + k, ki, i) ? 1 : 0;
+#pragma unroll 8
+    for (int k = 0; k < nj; ++k) {
+        const long long q = s_q[k], e = s_e[k];
+        const double ta = s_t[k];
+        const bool before =
+            (q < ki.qt) |
+            ((q == ki.qt) & ((e < ki.et) | ((e == ki.et) & ((ta < ki.ta) | ((ta == ki.ta) & (k < lim))))));
+        c += before ? 1 : 0;
+    }
     if (c) atomicAdd(&t.start[i], c);
 }
 
