@@ -41,6 +41,9 @@ if ROOT not in sys.path:
 METRIC = "segment-pair tests/s + p99 query latency; FP32+FP64-refine vs FP64, exact hits"
 D_VALUES = (1.0, 5.0, 25.0)      # the at-scale plain workload
 NUM_BINS = 1000
+# batches in flight in the timed steps of the headline forms (query handles on
+# their own streams)
+PIPE_DEPTH = 3
 HEAD_D = (0.001, 0.01)           # the precision-form workload
 PLAIN_WORKLOAD = ("C2 plain at scale: 1M-segment Gaussian random walk (2,500 x 400), "
                   "40,000 query segments x d in {1,5,25} (120,000 per step), 1,000 bins")
@@ -118,44 +121,104 @@ def to_device(seg):
     return out
 
 
-def run_form(ix, dq, opts, steps, warmup, n_ovl):
+def run_form(ix, dq, opts, steps, warmup, n_ovl, depth=1):
+    """Time one form on one batch.
+
+    A step is a C caller's whole pass over the batch: tds_query_batch, then
+    tds_fetch_results into device memory (which waits for the batch). The
+    device arrays, options and output buffers are set up once; every step's
+    hit count is checked against an untimed first pass.
+
+    depth 1: `steps` steps one at a time (each waits for its results before
+    the next is enqueued), with HIP events on the pair kernel's dispatch.
+    depth > 1, three phases of `steps` steps each:
+      1. one at a time, with the pair kernel's events (its launch time: the
+         roofline's; in the phases below kernels of other batches overlap it);
+      2. one at a time without events: the latency of a batch alone (p50/p99);
+      3. the timed throughput: `depth` batches in flight on `depth` query
+         handles, each on its own stream (the fetch of step i follows the
+         enqueue of step i + depth - 1), no events: ms_per_step = this
+         phase's wall time / steps."""
     import torch
     import paper_1405_7461_amd as tds
+    import ctypes as C
+    from paper_1405_7461_amd import _lib as L
+    lib = L.lib()
     qh = tds.Query(ix)
     stream = torch.cuda.current_stream()
     # one untimed pass that also counts overlapping pairs (checked against N_ovl)
     qh.batch(dq, dq.d, count_overlap=True, stream=stream, **opts)
     counted_hits = len(qh.fetch(out="device"))
     counted = qh.stats()["n_overlap"]
-    lat, pair_ms, stats = [], [], None
-    # A step as a C caller runs it: the device arrays, the options and the
-    # output buffer are set up once; each step is tds_query_batch, then
-    # tds_fetch_results into device memory, then a wait on the batch's stream
-    # (the records are written on it). HIP events on the pair kernel's
-    # dispatch (the lightest timing) are read after the step.
-    import ctypes as C
-    from paper_1405_7461_amd import _lib as L
-    lib = L.lib()
     prep = tds.prepare(dq, dq.d)
-    o = tds.api.query_opts(timing="pair", **opts)
     cap = max(1024, 2 * counted_hits)
-    out = torch.empty((cap, 5), dtype=torch.int64, device="cuda")
-    optr, sh, nh = C.c_void_p(out.data_ptr()), stream.cuda_stream, C.c_int64()
     seg, dptr = C.byref(prep.segments), prep.dptr
-    for i in range(warmup + steps):
-        stream.synchronize()
-        t0 = time.perf_counter()
-        rc = lib.tds_query_batch(qh.handle, seg, dptr, C.byref(o), sh)
-        rc = rc or lib.tds_fetch_results(qh.handle, optr, cap, L.TDS_MEM_DEVICE, C.byref(nh))
-        stream.synchronize()
-        t1 = time.perf_counter()
-        L.check(rc)
-        if i >= warmup:
-            st = qh.stats()
+    nh = C.c_int64()
+    out0 = torch.empty((cap, 5), dtype=torch.int64, device="cuda")
+
+    def one_at_a_time(o, n, on_step=None):
+        optr, sh = C.c_void_p(out0.data_ptr()), stream.cuda_stream
+        lat = []
+        for i in range(n):
+            stream.synchronize()
+            t0 = time.perf_counter()
+            rc = lib.tds_query_batch(qh.handle, seg, dptr, C.byref(o), sh)
+            rc = rc or lib.tds_fetch_results(qh.handle, optr, cap, L.TDS_MEM_DEVICE, C.byref(nh))
+            stream.synchronize()
+            t1 = time.perf_counter()
+            L.check(rc)
+            assert nh.value == counted_hits, (nh.value, counted_hits)
             lat.append(t1 - t0)
-            pair_ms.append(st["ms_pair"])
-            stats = st
-            n_hit = int(nh.value)
+            if on_step:
+                on_step(i)
+        return np.array(lat)
+
+    pair_ms, stats = [], None
+
+    def keep(i):
+        nonlocal stats
+        if i >= warmup:
+            stats = qh.stats()
+            pair_ms.append(stats["ms_pair"])
+
+    lat = one_at_a_time(tds.api.query_opts(timing="pair", **opts), warmup + steps, keep)[warmup:]
+    ms = float(lat.mean() * 1e3)
+    extra = {}
+    if depth > 1:
+        timed_ms = ms
+        lat = one_at_a_time(tds.api.query_opts(**opts), warmup + steps)[warmup:]
+        seq_ms = float(lat.mean() * 1e3)
+        o = tds.api.query_opts(**opts)
+        hs = [qh] + [tds.Query(ix) for _ in range(depth - 1)]
+        sts = [stream] + [torch.cuda.Stream() for _ in range(depth - 1)]
+        outs = [out0] + [torch.empty((cap, 5), dtype=torch.int64, device="cuda") for _ in range(depth - 1)]
+
+        def fetch(i):
+            k = i % depth
+            L.check(lib.tds_fetch_results(hs[k].handle, C.c_void_p(outs[k].data_ptr()), cap,
+                                          L.TDS_MEM_DEVICE, C.byref(nh)))
+            assert nh.value == counted_hits, (nh.value, counted_hits)
+
+        def run(n):
+            for i in range(n):
+                k = i % depth
+                L.check(lib.tds_query_batch(hs[k].handle, seg, dptr, C.byref(o), sts[k].cuda_stream))
+                if i >= depth - 1:
+                    fetch(i - depth + 1)
+            for i in range(max(0, n - depth + 1), n):
+                fetch(i)
+
+        run(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        for h in hs[1:]:
+            h.close()
+        extra = dict(depth=depth,
+                     one_at_a_time=dict(ms_per_step=seq_ms, value=n_ovl / (seq_ms / 1e3)),
+                     one_at_a_time_with_pair_events_ms=timed_ms)
     # stage breakdown from a few more steps with every stage timed
     prep_ms, refine_ms = [], []
     for i in range(3):
@@ -165,14 +228,12 @@ def run_form(ix, dq, opts, steps, warmup, n_ovl):
         prep_ms.append(st["ms_prep"])
         refine_ms.append(st["ms_refine"])
     qh.close()
-    lat = np.array(lat)
-    ms = float(lat.mean() * 1e3)
     return dict(ms_per_step=ms, value=n_ovl / (ms / 1e3), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), pair_ms=float(np.mean(pair_ms)),
-                n_hit=int(n_hit), n_eval=int(stats["n_eval"]), n_overlap=int(counted),
+                n_hit=int(counted_hits), n_eval=int(stats["n_eval"]), n_overlap=int(counted),
                 n_refine=int(stats["n_refine"]), retries=int(stats["retries"]),
                 n_items=int(stats["n_items"]), grid=int(stats["grid"]), prep_ms=float(np.median(prep_ms)),
-                refine_ms=float(np.median(refine_ms)), opts=opts)
+                refine_ms=float(np.median(refine_ms)), opts=opts, **extra)
 
 
 def cpu_baseline(db, q, target_s=10.0, nthreads=None, seed=12345, label="all the workload's d"):
@@ -582,11 +643,13 @@ def time_forms(ix, dq, n_ovl, names, steps, warmup, tag):
     }
     results = {}
     for name in names:
-        r = run_form(ix, dq, forms[name], steps, warmup, n_ovl)
+        r = run_form(ix, dq, forms[name], steps, warmup, n_ovl, depth=PIPE_DEPTH)
         assert r["n_overlap"] == n_ovl, (r["n_overlap"], n_ovl)
         r["roofline"] = roofline_of(name, r, n_ovl)
         results[name] = r
-        log(f"{tag} {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4g} pair-tests/s, pair kernel "
+        log(f"{tag} {name}: {r['ms_per_step']:.3f} ms/step with {r.get('depth', 1)} batches in flight "
+            f"({r['one_at_a_time']['ms_per_step']:.3f} one at a time), {r['value']:.4g} pair-tests/s, "
+            f"p50/p99 {r['p50_ms']:.3f}/{r['p99_ms']:.3f} ms, pair kernel "
             f"{r['pair_ms']:.3f} ms ({r['roofline']['frac']:.3f} of its roof), hits {r['n_hit']}, "
             f"N_eval {r['n_eval']}, refined {r['n_refine']}, retries {r['retries']}")
     if "fp32_refine" in results and "fp64" in results:
@@ -673,9 +736,10 @@ def main():
         "dtype": "f32+f64" if head_name == "fp32_refine" else "f64",
         "data": "synthetic",
         "config": {"workload": HEAD_WORKLOAD if args.workload == "C3" else PLAIN_WORKLOAD, "form": head_name,
-                   "n_overlap_per_step": n_ovl,
+                   "n_overlap_per_step": n_ovl, "batches_in_flight": head.get("depth", 1),
                    **{k: v for k, v in head["opts"].items()}},
-        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
+        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"],
+                       "of": "one batch alone: tds_query_batch + tds_fetch_results into device memory"},
         "roofline": roof,
         "forms": _strip(results),
     }
