@@ -60,6 +60,10 @@ __global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *
                 if constexpr (KIND == 17) asm volatile("v_max_f32 %0, %0, %1" : "+v"(a[k]) : "v"(b));
                 if constexpr (KIND == 18)
                     asm volatile("v_sub_f32_e64 %0, |%0|, %1" : "+v"(a[k]) : "v"(b));
+                if constexpr (KIND == 19)  // the multiplicand in a scalar register (the argument)
+                    asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[k]) : "s"(seed), "v"(c));
+                if constexpr (KIND == 20)
+                    asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(a[k]) : "s"(seed), "v"(c));
             }
         }
 #pragma unroll
@@ -115,7 +119,8 @@ extern "C" {
  * 7 v_max_f32 with absolute-value operands (VOP3 form), 8 v_pk_add_f16,
  * 9 v_min_f32, 10 v_cmp_le_f32 into a lane mask, 11 v_fma_f32, 12 v_fmac_f32,
  * 13 v_mul_f32, 14 v_add_f32, 15 v_or_b32, 16 v_or3_b32, 17 v_max_f32,
- * 18 v_sub_f32 with an absolute-value operand (VOP3 form)) with `blocks` workgroups of 256
+ * 18 v_sub_f32 with an absolute-value operand (VOP3 form), 19 v_fma_f32 and
+ * 20 v_fmac_f32 with the multiplicand in a scalar register) with `blocks` workgroups of 256
  * threads, each lane running `iters` iterations of 8 independent chain
  * steps, on `stream`, and waits for it.
  * Writes: *ms the kernel's duration (HIP events), *wave_instr the vector
@@ -126,7 +131,7 @@ extern "C" {
  */
 int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, double *wave_instr,
                    double *clock_hz) {
-    if (kind < 0 || kind > 18 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
+    if (kind < 0 || kind > 20 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
     hipStream_t s = (hipStream_t)stream;
     const int waves = blocks * (kBlock / 64);
     float *sink = nullptr;
@@ -159,7 +164,9 @@ int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, do
             case 15: err = run_kind<15>(blocks, iters, seed, sink, st, s); break;
             case 16: err = run_kind<16>(blocks, iters, seed, sink, st, s); break;
             case 17: err = run_kind<17>(blocks, iters, seed, sink, st, s); break;
-            default: err = run_kind<18>(blocks, iters, seed, sink, st, s); break;
+            case 18: err = run_kind<18>(blocks, iters, seed, sink, st, s); break;
+            case 19: err = run_kind<19>(blocks, iters, seed, sink, st, s); break;
+            default: err = run_kind<20>(blocks, iters, seed, sink, st, s); break;
             }
         }
         if (err == hipSuccess) err = hipEventRecord(e1, s);
