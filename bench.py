@@ -599,7 +599,8 @@ def valu_probe(log_fn=log):
     names = ("v_sub_f32", "v_max3_f32_abs", "v_min3_f32", "v_fma_f64", "v_add_u32", "v_pk_sub_u16",
              "v_pk_max_u16", "v_max_f32_e64_abs", "v_pk_add_f16", "v_min_f32", "v_cmp_le_f32",
              "v_fma_f32", "v_fmac_f32", "v_mul_f32", "v_add_f32", "v_or_b32", "v_or3_b32", "v_max_f32",
-             "v_sub_f32_e64_abs", "v_fma_f32_sgpr", "v_fmac_f32_sgpr")
+             "v_sub_f32_e64_abs", "v_fma_f32_sgpr", "v_fmac_f32_sgpr", "v_fma_f32_3banks",
+             "v_fma_f32_same_bank")
     for kind, name in enumerate(names):
         best = None
         for _ in range(3):

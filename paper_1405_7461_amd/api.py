@@ -337,6 +337,12 @@ class Query:
         L.check(L.lib().tds_query_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in L.tds_stats._fields_}
 
+    def device_bytes(self) -> int:
+        """Device memory the handle holds now (tds_query_device_bytes)."""
+        n = C.c_int64()
+        L.check(L.lib().tds_query_device_bytes(self._h, C.byref(n)))
+        return int(n.value)
+
     def tiles(self):
         """Tiles of the last fetched batch and the caller indices in tile order.
 

@@ -937,9 +937,13 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 }
                 const float H = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(hmax)));
                 const float E2 = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(e2max)));
-                // s = e2 + (-2C).c with one multiply-add per axis
+                // s = e2 + (-2C).c with one multiply-add per axis; a staged
+                // query is (T, -2C): component k of the query then sits one
+                // register after component k of the entry, in another
+                // register bank of the four (a multiply-add whose sources
+                // share a bank issues slower)
                 auto dot_of = [&](const float4 &c, const float4 &q) {
-                    return __builtin_fmaf(c.z, q.z, __builtin_fmaf(c.y, q.y, __builtin_fmaf(c.x, q.x, c.w)));
+                    return __builtin_fmaf(c.z, q.w, __builtin_fmaf(c.y, q.z, __builtin_fmaf(c.x, q.y, c.w)));
                 };
                 // Smallest s of a staged query over the lane's slots.
                 auto gmin_of = [&](const float4 &qv, auto full) {
@@ -959,7 +963,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     for (int j = 0; j < EPT; ++j) {
                         const bool has = FULL || j < nv;  // wave-uniform
                         const float g = has ? dot_of(ec[j], qv) : NAN;
-                        select(g <= qv.w, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                        select(g <= qv.x, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
                     }
                 };
                 auto count_ovl = [&](const int qs) {
@@ -974,7 +978,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     }
                 };
                 // The wave stages up to 64 query balls in its LDS slice (one
-                // coalesced load, lane i takes ball s0 + i) as (-2C, T), T the
+                // coalesced load, lane i takes ball s0 + i) as (T, -2C), T the
                 // ball's threshold against this chunk, evaluated in binary64
                 // with margins for its own rounding and rounded up:
                 //   T = (r + H)^2 - |C|^2 + kDotSlack (E2 + |C|^2);
@@ -991,14 +995,14 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         const int ns = __builtin_amdgcn_readfirstlane(min(kStage, qe - s0));
                         if (lane < ns) {
                             const QCube32 c = box[perm[s0 + lane]];
-                            float4 v = make_float4(0.0f, 0.0f, 0.0f, INFINITY);  // passes all
+                            float4 v = make_float4(INFINITY, 0.0f, 0.0f, 0.0f);  // passes all
                             if (c.r != INFINITY) {
                                 const double C2 = (double)c.cx * c.cx + (double)c.cy * c.cy +
                                                   (double)c.cz * c.cz;
                                 const double R = (double)c.r + (double)H;
                                 const double T = R * R * (1.0 + 0x1p-40) - C2 * (1.0 - 0x1p-40) +
                                                  kDotSlack * ((double)E2 + C2);
-                                v = make_float4(-2.0f * c.cx, -2.0f * c.cy, -2.0f * c.cz, f32_up(T));
+                                v = make_float4(f32_up(T), -2.0f * c.cx, -2.0f * c.cy, -2.0f * c.cz);
                             }
                             s_q[wv][lane] = v;
                         }
@@ -1009,7 +1013,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
 #pragma unroll
                             for (int k = 0; k < kGroup; ++k) {
                                 const float4 qk = sq[j + k];
-                                p |= gmin_of(qk, full) <= qk.w;
+                                p |= gmin_of(qk, full) <= qk.x;
                             }
                             if (__builtin_expect(__ballot(p) != 0ull, 0)) {
                                 for (int k = 0; k < kGroup; ++k) emit(sq[j + k], s0 + j + k, full);
@@ -1019,7 +1023,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                         for (; j + kGroup <= ns; j += kGroup) group(j);
                         for (; j < ns; ++j) {
                             const float4 qa = sq[j];
-                            if (__builtin_expect(__ballot(gmin_of(qa, full) <= qa.w) != 0ull, 0))
+                            if (__builtin_expect(__ballot(gmin_of(qa, full) <= qa.x) != 0ull, 0))
                                 emit(qa, s0 + j, full);
                         }
                         if (COUNT_OVL)

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *
     float acc = 0.0f;
     // The chain steps are written as inline assembly (register operands
     // only, no memory access) so that exactly the named instruction is timed.
-    if constexpr (KIND <= 2 || (KIND >= 4 && KIND <= 9) || KIND >= 11) {
+    if constexpr (KIND <= 2 || (KIND >= 4 && KIND <= 9) || (KIND >= 11 && KIND <= 20)) {
         float a[kChains];
         float b = seed * 1e-7f + lane * 1e-9f, c = seed * 3e-7f;
 #pragma unroll
@@ -83,6 +83,33 @@ __global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *
             }
         }
         acc = (float)(m & 1);
+    } else if constexpr (KIND == 21 || KIND == 22) {
+        // v_fma_f32 on fixed registers, eight chains in v40, v44, ..., v68
+        // (all in register bank 0 of 4, bank = number mod 4): 21 with the
+        // other two sources in banks 1 and 2, 22 with the second multiplicand
+        // in bank 0 as well (the two multiplicands in one bank)
+        asm volatile(
+            "v_mov_b32 v40, 1.0\n v_mov_b32 v44, 1.0\n v_mov_b32 v48, 1.0\n v_mov_b32 v52, 1.0\n"
+            "v_mov_b32 v56, 1.0\n v_mov_b32 v60, 1.0\n v_mov_b32 v64, 1.0\n v_mov_b32 v68, 1.0\n"
+            "v_mov_b32 v72, 1.0\n v_mov_b32 v73, 1.0\n v_mov_b32 v74, 0\n" ::
+                : "v40", "v44", "v48", "v52", "v56", "v60", "v64", "v68", "v72", "v73", "v74");
+        for (int i = 0; i < iters; ++i) {
+            if constexpr (KIND == 21)
+                asm volatile(
+                    "v_fma_f32 v40, v40, v73, v74\n v_fma_f32 v44, v44, v73, v74\n"
+                    "v_fma_f32 v48, v48, v73, v74\n v_fma_f32 v52, v52, v73, v74\n"
+                    "v_fma_f32 v56, v56, v73, v74\n v_fma_f32 v60, v60, v73, v74\n"
+                    "v_fma_f32 v64, v64, v73, v74\n v_fma_f32 v68, v68, v73, v74\n" ::
+                        : "v40", "v44", "v48", "v52", "v56", "v60", "v64", "v68");
+            else
+                asm volatile(
+                    "v_fma_f32 v40, v40, v72, v74\n v_fma_f32 v44, v44, v72, v74\n"
+                    "v_fma_f32 v48, v48, v72, v74\n v_fma_f32 v52, v52, v72, v74\n"
+                    "v_fma_f32 v56, v56, v72, v74\n v_fma_f32 v60, v60, v72, v74\n"
+                    "v_fma_f32 v64, v64, v72, v74\n v_fma_f32 v68, v68, v72, v74\n" ::
+                        : "v40", "v44", "v48", "v52", "v56", "v60", "v64", "v68");
+        }
+        acc = seed;
     } else if constexpr (KIND == 3) {
         double a[kChains], b = 1.0 + seed * 1e-9, c = seed * 1e-12 + lane * 1e-15;
 #pragma unroll
@@ -120,7 +147,9 @@ extern "C" {
  * 9 v_min_f32, 10 v_cmp_le_f32 into a lane mask, 11 v_fma_f32, 12 v_fmac_f32,
  * 13 v_mul_f32, 14 v_add_f32, 15 v_or_b32, 16 v_or3_b32, 17 v_max_f32,
  * 18 v_sub_f32 with an absolute-value operand (VOP3 form), 19 v_fma_f32 and
- * 20 v_fmac_f32 with the multiplicand in a scalar register) with `blocks` workgroups of 256
+ * 20 v_fmac_f32 with the multiplicand in a scalar register, 21 v_fma_f32 with
+ * its three sources in three register banks, 22 v_fma_f32 with its two
+ * multiplicands in one bank) with `blocks` workgroups of 256
  * threads, each lane running `iters` iterations of 8 independent chain
  * steps, on `stream`, and waits for it.
  * Writes: *ms the kernel's duration (HIP events), *wave_instr the vector
@@ -131,7 +160,7 @@ extern "C" {
  */
 int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, double *wave_instr,
                    double *clock_hz) {
-    if (kind < 0 || kind > 20 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
+    if (kind < 0 || kind > 22 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
     hipStream_t s = (hipStream_t)stream;
     const int waves = blocks * (kBlock / 64);
     float *sink = nullptr;
@@ -166,7 +195,9 @@ int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, do
             case 17: err = run_kind<17>(blocks, iters, seed, sink, st, s); break;
             case 18: err = run_kind<18>(blocks, iters, seed, sink, st, s); break;
             case 19: err = run_kind<19>(blocks, iters, seed, sink, st, s); break;
-            default: err = run_kind<20>(blocks, iters, seed, sink, st, s); break;
+            case 20: err = run_kind<20>(blocks, iters, seed, sink, st, s); break;
+            case 21: err = run_kind<21>(blocks, iters, seed, sink, st, s); break;
+            default: err = run_kind<22>(blocks, iters, seed, sink, st, s); break;
             }
         }
         if (err == hipSuccess) err = hipEventRecord(e1, s);

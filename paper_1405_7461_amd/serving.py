@@ -15,7 +15,11 @@ the hit fraction alpha is tracked per temporal epoch (50 epochs over the
 database's time extent), and a query segment's expected hits are alpha of
 its epoch times its number of candidate entries (computed on the host from
 the bin table). Alpha is updated from every completed batch, and a waiting
-request is estimated again each time a batch is formed. A batch whose
+request is estimated again each time a batch is formed. The device memory
+each executor's query handle holds (its buffers grow and are kept) counts
+against the pool too: a batch is admitted on an executor when the other
+executors' holdings (or their in-flight estimates, if larger) plus the
+larger of this executor's holding and the batch's estimate fit. A batch whose
 estimate is too small still completes: the library re-runs the pair kernel
 with a larger buffer. The library's native scheduler (tds_server_*, the
 NativeServer binding) follows the same policy; this one keeps it in Python
@@ -101,6 +105,10 @@ class GpuExecutor:
         h = self.qh.fetch(out="host")
         return h, self.qh.stats()
 
+    def device_bytes(self) -> int:
+        """Device memory the executor's query handle holds (kept between batches)."""
+        return self.qh.device_bytes()
+
     def close(self):
         self.qh.close()
 
@@ -135,6 +143,11 @@ class Server:
         self.executors = [factory() for _ in range(self.streams)]
         self.lock = threading.Lock()
         self.in_flight_bytes = 0.0
+        # device bytes each executor's handle holds after its last batch
+        # (buffers grow and are kept); counted against the pool with the
+        # estimates of the batches in flight
+        self.reserved = [0.0] * self.streams
+        self.in_flight = [0.0] * self.streams
         self.batches: List[Dict] = []
 
     # -------------------------------------------------------------- planning
@@ -169,7 +182,7 @@ class Server:
         process did not.
         The hit-rate estimates learnt here are kept; the batch log is not.
         """
-        for ex in self.executors:
+        for k, ex in enumerate(self.executors):
             for r in requests:
                 self.plan(r)
                 cap = int(r.est_bytes / HIT_BYTES) + 1024
@@ -186,6 +199,8 @@ class Server:
                     for f in FIELDS:
                         setattr(big, f, np.tile(getattr(seg, f), reps)[:reserve_segments])
                     ex(big, np.tile(d, reps)[:reserve_segments], int(self.pool_bytes / HIT_BYTES) + 1024)
+            if hasattr(ex, "device_bytes"):
+                self.reserved[k] = float(ex.device_bytes())
         if requests:
             replay = [Request(rid=k, seg=r.seg, d=r.d, arrival=2e-4 * k)
                       for k, r in enumerate(list(requests) * 4)]
@@ -239,11 +254,15 @@ class Server:
                     r.hits = api.Hits(hq[sel] - off[k], np.asarray(h.entry)[sel], np.asarray(h.traj)[sel],
                                       np.asarray(h.ta)[sel], np.asarray(h.tb)[sel])
                     r.t_done = t_end
+                dev = getattr(self.executors[ei], "device_bytes", None)
                 with self.lock:
                     t0_all = np.concatenate([np.asarray(r.seg.t0) for r in batch])
                     ev_all = np.concatenate([r._n_eval_seg for r in batch])
                     self.alpha.update(t0_all, ev_all, hits_seg)
                     self.in_flight_bytes -= cap_bytes
+                    self.in_flight[ei] = 0.0
+                    if dev is not None:
+                        self.reserved[ei] = float(dev())
                     self.batches.append(dict(n_req=len(batch), n_seg=int(off[-1]), hits=len(hq),
                                              t_launch=t_launch, t_end=t_end, retries=st["retries"],
                                              ms_pair=st.get("ms_pair", 0.0)))
@@ -271,13 +290,19 @@ class Server:
                 if ei is not None:
                     batch, nseg, nbytes = [], 0, 0.0
                     with self.lock:
-                        budget = self.pool_bytes - self.in_flight_bytes
+                        # the other executors hold their buffers, or more
+                        # while a batch of theirs is in flight; this one
+                        # needs the larger of its buffers and the estimate
+                        others = sum(max(self.reserved[x], self.in_flight[x])
+                                     for x in range(self.streams) if x != ei)
                         while pending:
                             r = pending[0]
                             # waiting requests are re-estimated with the alpha
                             # the batches completed so far have updated
                             self.estimate(r)
-                            fits = (nbytes + r.est_bytes <= budget or not batch and self.in_flight_bytes == 0)
+                            need = max(self.reserved[ei], nbytes + r.est_bytes)
+                            fits = (others + need <= self.pool_bytes
+                                    or not batch and self.in_flight_bytes == 0)
                             if not fits or (batch and nseg + r.n > self.max_batch_segments):
                                 break
                             pending.popleft()
@@ -286,6 +311,7 @@ class Server:
                             nbytes += r.est_bytes
                         if batch:
                             self.in_flight_bytes += nbytes
+                            self.in_flight[ei] = nbytes
                     if batch:
                         ta = now()
                         for r in batch:

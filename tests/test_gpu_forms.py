@@ -36,12 +36,19 @@ def test_serving_alone_equals_mixed():
         qh.batch(r.seg, r.d, mode="fp32_refine", tiling="range")
         alone[r.rid] = qh.fetch().sorted()
     qh.close()
-    arr = poisson_arrivals(len(reqs), rate=400.0, seed=11)
+    # arrivals faster than the two streams serve them one by one, so
+    # requests wait and are batched together
+    arr = poisson_arrivals(len(reqs), rate=20000.0, seed=11)
     for r, a in zip(reqs, arr):
         r.arrival = float(a)
-    # a small result pool forces several batches; two streams overlap them
-    srv = Server(ix, pool_bytes=2e5, streams=2, k_safety=2.0,
+    # the executors' buffers, grown by a warm-up, count against the pool,
+    # with 2e5 bytes of result estimates beyond them; two streams overlap
+    # the batches
+    srv = Server(ix, pool_bytes=64e6, streams=2, k_safety=2.0,
                  opts=dict(mode="fp32_refine", tiling="range"))
+    srv.warmup(reqs[:2])
+    assert min(srv.reserved) > 0
+    srv.pool_bytes = sum(srv.reserved) + 2e5
     stats = srv.run(reqs)
     srv.close()
     say(f"serving: {stats}")
