@@ -149,6 +149,9 @@ typedef struct {
     float ms_pair;       /* pair kernel (last launch) */
     float ms_fetch;      /* result translation + copy */
     float ms_refine;     /* refine kernel (last launch) */
+    int32_t chunk;       /* entries per chunk: a work unit pairs one query segment with at most
+                            this many consecutive candidate entries (64 x entries per lane) */
+    int32_t reserved1;
 } tds_stats;
 
 typedef struct {

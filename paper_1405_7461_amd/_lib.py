@@ -74,7 +74,8 @@ class tds_stats(C.Structure):
                 ("n_overlap_k", C.c_int64), ("n_refine", C.c_int64), ("n_hit", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_items", C.c_int64), ("retries", C.c_int32),
                 ("grid", C.c_int32), ("ms_prep", C.c_float), ("ms_pair", C.c_float),
-                ("ms_fetch", C.c_float), ("ms_refine", C.c_float)]
+                ("ms_fetch", C.c_float), ("ms_refine", C.c_float), ("chunk", C.c_int32),
+                ("reserved1", C.c_int32)]
 
 
 class tds_index_info(C.Structure):

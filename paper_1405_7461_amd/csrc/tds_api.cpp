@@ -991,6 +991,7 @@ static int complete_batch(tds_query *q, const char *who) {
         q->n_sorted = (int64_t)c.n_sorted;
         s.n_items = (int64_t)c.n_units;
         s.grid = q->grid;
+        s.chunk = q->b.chunk;
         s.retries = retries;
         // timing: the event times are read by tds_query_stats, outside the batch's path
         q->fetch_timed = false;

@@ -759,7 +759,7 @@ __device__ __forceinline__ void set_prio(int p) {
 
 // Entries per lane: each wave holds 64 * EPT candidate entries of a chunk.
 #ifndef TDS_EPT32
-#define TDS_EPT32 4
+#define TDS_EPT32 5
 #endif
 #ifndef TDS_EPT64
 #define TDS_EPT64 2

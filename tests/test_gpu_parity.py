@@ -395,7 +395,7 @@ def test_outlier_band_stays_local():
     # query segments whose range holds the outlier's chunk (time step 200)
     n_step = int(np.sum((q.t0 < 201.0) & (q.t1 > 200.0)))
     say(f"outlier: refined {st1['n_refine']} -> {st2['n_refine']} ({n_step} query segments at its step)")
-    assert st2["n_refine"] - st1["n_refine"] <= 256 * n_step
+    assert st2["n_refine"] - st1["n_refine"] <= st2["chunk"] * n_step
     assert st2["n_refine"] < st1["n_refine"] + 0.05 * st2["n_eval"]
 
 
