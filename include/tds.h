@@ -147,7 +147,7 @@ typedef struct {
     int32_t grid;        /* pair-kernel workgroups used */
     float ms_prep;       /* TDS_QF_TIMING: query preparation, sort and tiling */
     float ms_pair;       /* pair kernel (last launch) */
-    float ms_fetch;      /* result translation + copy */
+    float ms_fetch;      /* the batch's last kernel at fetch: hit offsets, records, counters */
     float ms_refine;     /* refine kernel (last launch) */
     int32_t chunk;       /* entries per chunk: a work unit pairs one query segment with at most
                             this many consecutive candidate entries (64 x entries per lane) */
@@ -258,7 +258,8 @@ int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
 /*
  * Wait for the batch, re-run the pair kernel with a larger result buffer if
  * it overflowed (Sec. 5: re-attempt with more memory), translate to caller
- * indices and write min(cap, n) records to `out` (host memory when out_mem is
+ * indices and write min(cap, n) records to `out` in an unspecified order
+ * (host memory when out_mem is
  * TDS_MEM_HOST, device memory for TDS_MEM_DEVICE). *n_total always receives
  * the number of hits, so cap = 0 sizes the buffer. Host output is complete on
  * return; device output is written on the batch's stream, so work on another
@@ -356,10 +357,10 @@ int tds_set_allocator(tds_alloc_fn alloc, tds_free_fn free_fn, void *ctx);
  * memory, event or stream is created.
  *
  * q and d must be in device memory (TDS_MEM_DEVICE); out is device memory
- * for cap records (cap = 0 only counts). The call enqueues the search on
- * `stream`, waits for it (it reads the hit count), enqueues the translation
- * of min(cap, n) records into `out` on `stream` and returns: *n_total is the
- * number of hits, and `out` is complete once `stream` reaches that point.
+ * for cap records (cap = 0 only counts). The call enqueues the search and
+ * the writing of min(cap, n) records into `out` on `stream`, waits for it
+ * (it reads the hit count) and returns: *n_total is the number of hits and
+ * `out` is complete. On an error the contents of `out` are unspecified.
  * Options are those of tds_query_batch; capacity and max_retries are
  * ignored: the result slabs take whatever scratch the batch leaves free.
  *

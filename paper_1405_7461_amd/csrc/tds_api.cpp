@@ -192,10 +192,11 @@ struct tds_query {
     long long nslabs_alloc = 0;    // slabs the cand / hits buffers hold
     int32_t nwaves_alloc = 0;      // wave slabs slab_n / wave_ovl hold
     Counters *host_ctr = nullptr;  // pinned
-    // The batch counters live in two slots used in turn: the hit scan of a
-    // batch clears the other slot and the bucket counters, so the next batch
-    // starts without a clearing kernel. clear_needed: they were not cleared
-    // (new buffers, a batch without segments, an error).
+    // The batch counters live in two slots used in turn: the last kernel of
+    // a batch (k_emit, enqueued at fetch) clears the other slot and the
+    // bucket counters, so the next batch starts without a clearing kernel.
+    // clear_needed: they were not cleared (new buffers, a batch without
+    // segments, an error).
     int ctr_slot = 0;
     bool clear_needed = true;
     NextClear next{};
@@ -204,6 +205,7 @@ struct tds_query {
     tds_query_opts opts{};
     int block = 256, grid = 0;
     bool pending = false, fetched = false;
+    bool emitted = false;     // k_emit is enqueued after the last search run
     int64_t n_sorted = 0;     // query segments placed in tiles (last fetched batch)
     bool fetch_timed = false; // ev[4], ev[5] bracket the last fetch's translation
     bool traj_valid = false;  // tr_out holds the merged records of this batch
@@ -705,24 +707,40 @@ static unsigned long long spill_capacity(const Slabs &sl) {
     return (unsigned long long)(sl.nslabs - sl.nwaves);
 }
 
-// Pair kernel (selects pairs), then refine (turns them into hits) and the hit
-// scan, with HIP events around the pair kernel and the refine when timing is
-// on; the counters are copied back on the same stream.
+// Pair kernel (selects pairs), then refine (turns them into hits), with HIP
+// events around the pair kernel and the refine when timing is on. The
+// batch's last kernel (k_emit: offsets, records, final counters) follows at
+// fetch; a batch without query segments has none, so its counters are
+// copied here.
 static int launch_search(tds_query *q) {
     const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
     const int kovl = (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
     // timing: events attached to the pair kernel's dispatch (start, end) and
-    // to the end of the hit scan
+    // to the end of the refine
     const bool tpair = timing || (q->opts.flags & TDS_QF_TIMING_PAIR) != 0;
     HIP_TRY(launch_pair(q->b, q->ix->dev, q->opts.mode, q->block, q->opts.grid, kovl, q->sl,
                         q->stream, tpair ? q->ev[1] : nullptr, tpair ? q->ev[2] : nullptr));
-    // the scan kernel writes the final counters to host_ctr itself; a batch
-    // without query segments launches no scan, so its counters are copied
-    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, kovl, q->stream, timing ? q->ev[3] : nullptr,
-                          q->host_ctr, q->next));
+    HIP_TRY(launch_refine(q->b, q->ix->dev, q->sl, q->stream, timing ? q->ev[3] : nullptr));
     if (q->b.nq == 0)
         HIP_TRY(hipMemcpyAsync(q->host_ctr, q->b.ctr, sizeof(Counters), hipMemcpyDeviceToHost,
                                q->stream));
+    q->emitted = false;
+    return TDS_OK;
+}
+
+// The batch's last kernel with `n` records to `out` (null: offsets and
+// counters only); it writes the final counters to host_ctr and clears the
+// next batch's counters. The fetch's timing events bracket it when it writes
+// records.
+static int enqueue_emit(tds_query *q, void *out, int64_t n) {
+    if (q->b.nq > 0) {
+        const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0 && out;
+        const int kovl = (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
+        HIP_TRY(launch_emit(q->sl, q->b.ctr, n, q->b.perm, q->ix->dev, out, kovl, q->host_ctr,
+                            q->next, q->stream, timing ? q->ev[4] : nullptr,
+                            timing ? q->ev[5] : nullptr));
+    }
+    q->emitted = true;
     return TDS_OK;
 }
 
@@ -858,7 +876,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     b.unit_off = q->unit_off.as<long long>();
     b.cost_off = q->cost_off.as<long long>();
     b.ctr = q->ctr.as<Counters>() + q->ctr_slot;
-    // the hit scan of this batch clears the next batch's counters
+    // the last kernel of this batch clears the next batch's counters
     q->next = NextClear{q->ctr.as<Counters>() + (q->ctr_slot ^ 1), q->bcount.as<int32_t>(),
                         q->bj2.as<int32_t>(), q->cap_buckets, 0};
 
@@ -885,7 +903,7 @@ int tds_query_batch(tds_query *q, const tds_segments *qs, const double *d,
     if (rc) return rc;
     rc = launch_search(q);
     if (rc) return rc;
-    // a batch without segments launches no hit scan, which would clear
+    // a batch without segments launches no k_emit, which would clear
     q->clear_needed = nq == 0;
     q->ctr_slot ^= 1;
     q->pending = true;
@@ -948,6 +966,10 @@ int tds_query_device_bytes(const tds_query *q, int64_t *bytes) {
 static int complete_batch(tds_query *q, const char *who) {
     hipStream_t st = q->stream;
     if (q->pending) {
+        if (!q->emitted) {
+            int rc = enqueue_emit(q, nullptr, 0);
+            if (rc) return rc;
+        }
         HIP_TRY(hipStreamSynchronize(st));
         Counters c = *q->host_ctr;
         if (c.err) {
@@ -976,6 +998,8 @@ static int complete_batch(tds_query *q, const char *who) {
             if (rc) return rc;
             HIP_TRY(launch_reset_counters(q->b.ctr, 1, st));
             rc = launch_search(q);
+            if (rc) return rc;
+            rc = enqueue_emit(q, nullptr, 0);
             if (rc) return rc;
             q->clear_needed = false;
             HIP_TRY(hipStreamSynchronize(st));
@@ -1010,23 +1034,17 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
     if (!q->pending && !q->fetched) return fail(TDS_ESTATE, "tds_fetch_results: no batch");
     hipStream_t st = q->stream;
     const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
-    // A pending batch: the translation is enqueued before the host waits (it
-    // reads the hit count on the device and writes at most cap records), so
-    // the device does not idle while the host wakes up. It is redone below
-    // if the batch had to be re-run or holds more hits than cap.
-    // Host output is staged on the device first; the early translation only
-    // uses staging that is already large enough (a generous cap allocates
-    // nothing before the count is known).
+    // A pending batch: its last kernel (offsets, at most cap records, the
+    // counters) is enqueued before the host waits, so the device does not
+    // idle while the host wakes up. It runs again below if the batch had to
+    // be re-run. Host output is staged on the device first; the early run
+    // only uses staging that is already large enough (a generous cap
+    // allocates nothing before the count is known).
     bool early = false;
     const bool stage_fits = (size_t)cap * sizeof(tds_hit) <= q->out_stage.bytes;
     if (q->pending && cap > 0 && (out_mem == TDS_MEM_DEVICE || stage_fits)) {
-        if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
-        if (out_mem == TDS_MEM_DEVICE)
-            HIP_TRY(launch_translate(q->sl, q->b.ctr, cap, q->b.perm, q->ix->dev, out, st));
-        else
-            HIP_TRY(launch_translate(q->sl, q->b.ctr, cap, q->b.perm, q->ix->dev, q->out_stage.p,
-                                     st));
-        if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
+        int rc = enqueue_emit(q, out_mem == TDS_MEM_DEVICE ? (void *)out : q->out_stage.p, cap);
+        if (rc) return rc;
         early = true;
     }
     if (q->pending) {
@@ -1037,16 +1055,10 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
     *n_total = n;
     const int64_t m = std::min<int64_t>(cap, n);
     if (m > 0) {
-        if (!early || q->stats.retries > 0) {  // translate now
-            if (timing) HIP_TRY(hipEventRecord(q->ev[4], st));
-            if (out_mem == TDS_MEM_DEVICE) {
-                HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, out, st));
-            } else {
-                HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
-                HIP_TRY(launch_translate(q->sl, q->b.ctr, m, q->b.perm, q->ix->dev, q->out_stage.p,
-                                         st));
-            }
-            if (timing) HIP_TRY(hipEventRecord(q->ev[5], st));
+        if (!early || q->stats.retries > 0) {  // the records now
+            if (out_mem == TDS_MEM_HOST) HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
+            int rc = enqueue_emit(q, out_mem == TDS_MEM_DEVICE ? (void *)out : q->out_stage.p, m);
+            if (rc) return rc;
         }
         if (out_mem == TDS_MEM_HOST) {
             HIP_TRY(hipMemcpyAsync(out, q->out_stage.p, (size_t)m * sizeof(tds_hit),
@@ -1318,7 +1330,10 @@ int tds_search_noalloc(const tds_index *ix, const tds_segments *qs, const double
     if (rc) return rc;
     if (nq > 0) {
         HIP_TRY(launch_pair(b, ix->dev, o.mode, o.block_size, o.grid, kovl, sl, st));
-        HIP_TRY(launch_refine(b, ix->dev, sl, kovl, st, nullptr, nullptr));
+        HIP_TRY(launch_refine(b, ix->dev, sl, st));
+        // offsets, counters and the first cap records in one kernel
+        HIP_TRY(launch_emit(sl, b.ctr, cap, b.perm, ix->dev, cap > 0 ? (void *)out : nullptr, kovl,
+                            nullptr, NextClear{}, st));
     }
     Counters ctr{};
     HIP_TRY(hipMemcpyAsync(&ctr, b.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));
@@ -1332,8 +1347,6 @@ int tds_search_noalloc(const tds_index *ix, const tds_segments *qs, const double
                     "the scratch holds %lld",
                     who, ctr.spill, kSlab, (long long)(sl.nslabs - sl.nwaves));
     *n_total = (int64_t)ctr.hits;
-    const int64_t m = std::min<int64_t>(cap, (int64_t)ctr.hits);
-    if (m > 0) HIP_TRY(launch_translate(sl, b.ctr, m, b.perm, ix->dev, out, st));
     return TDS_OK;
 }
 

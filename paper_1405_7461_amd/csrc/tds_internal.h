@@ -185,15 +185,15 @@ struct Hit24 {
 // slab from the spill slabs after the wave slabs (one atomic per 64 records
 // at most) and leaves the old one partly filled. Every slab carries its own
 // record count. Hit slab s holds the hits among selected-pair slab s, and
-// k_hit_scan's offsets give the position of each slab's hits in the dense
-// output.
+// the offsets k_emit writes give the position of each slab's hits in the
+// dense output.
 constexpr int kSlab = 64;
 struct Slabs {
     Cand *cand;                    // nslabs * kSlab
     Hit24 *hits;                   // nslabs * kSlab
     int32_t *slab_n;               // selected pairs in each slab [nslabs]
     int32_t *slab_h;               // hits in each slab [nslabs]
-    long long *hit_off;            // exclusive scan of slab_h [nslabs + 1]
+    long long *hit_off;            // exclusive scan of slab_h [nslabs]
     unsigned long long *wave_ovl;  // overlapping pairs counted by each wave [nwaves]
     int32_t nwaves;                // waves of the pair launch (= wave slabs)
     int32_t pad;
@@ -372,7 +372,7 @@ hipError_t launch_ingest(const double *const *raw, int64_t n, const int32_t *per
                          int64_t *traj, hipStream_t st);
 // ev_start (optional) records the start of the first kernel. With zero
 // false the per-bucket counters and the batch counters are taken as already
-// cleared (the previous batch's hit scan cleared them, see NextClear).
+// cleared (the previous batch's last kernel, k_emit, cleared them, see NextClear).
 hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, DevIndex ix,
                           hipStream_t st, hipEvent_t ev_start = nullptr, bool zero = true);
 // What the last kernel of a batch clears for the next batch of the same
@@ -394,12 +394,14 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
 // Refine the selected pairs into hit slabs, then scan the hit counts;
 // ev_stop (optional) records the end of the scan.
 // host_out (optional): pinned host copy of the final counters, written by the scan.
-hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
-                         hipEvent_t ev_stop = nullptr, Counters *host_out = nullptr,
-                         NextClear next = NextClear{});
-// Dense caller-index records of the first n hits.
-hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
-                            DevIndex ix, void *out_hits, hipStream_t st);
+hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, hipStream_t st,
+                         hipEvent_t ev_stop = nullptr);
+// The batch's last kernel: hit offsets, the dense caller-index records of the
+// first n hits (none when out_hits is null), the final counters (also to
+// host_out when not null) and the clearing of the next batch's counters.
+hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, const int32_t *perm, DevIndex ix,
+                       void *out_hits, int count_ovl, Counters *host_out, NextClear next,
+                       hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
 // Trajectory merge (tds_traj.hip): temp bytes for n hits, and the launch
 // (n > 0 hits; writes the merged records to `out` and their number to *total).

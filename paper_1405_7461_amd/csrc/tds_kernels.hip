@@ -413,11 +413,16 @@ constexpr int kScanBlock = 1024;
 // registers for both passes (longer runs read them again).
 constexpr int kBucketRun = 4;
 
-__global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex ix) {
+// The scan of one workgroup of kScanBlock threads. publish: write the
+// offsets (bq_off), the tiles, their unit and cost offsets and the counters;
+// s_off (optional, LDS): the offset of every bucket, for the scatter of the
+// same workgroup.
+__device__ __forceinline__ void bucket_scan_body(const DevBatch &b, const DevIndex &ix, int *s_off,
+                                                 bool publish) {
     const int n = b.nbuckets;
     const int per = (n + kScanBlock - 1) / kScanBlock;
     const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
-    const bool range = b.tiling == kTileRange;
+    const bool range = publish && b.tiling == kTileRange;
     const bool held = per <= kBucketRun;
     int hc[kBucketRun], he0[kBucketRun], hne[kBucketRun];
     auto count_of = [&](int k) {
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
         int c, e0, ne;
         get(r, &c, &e0, &ne);
         c_sum += c;
-        if (!range && c > kSortLds) atomicAdd(&b.ctr->big_bins, 1u);
+        if (publish && b.tiling != kTileRange && c > kSortLds) atomicAdd(&b.ctr->big_bins, 1u);
         if (range && c > 0) {
             const int nch = (ne + b.chunk - 1) / b.chunk;
             t_sum += 1;
@@ -488,10 +493,13 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
         int c, e0, ne;
         get(r, &c, &e0, &ne);
         int part = 0;
+        if (s_off) s_off[k] = (int)c_run;
+        if (publish) {
 #pragma unroll
-        for (int j = 0; j < kBucketSub; ++j) {
-            b.bq_off[k * kBucketSub + j] = (int)c_run + part;
-            if (kBucketSub > 1) part += b.bcount[k * kBucketSub + j];
+            for (int j = 0; j < kBucketSub; ++j) {
+                b.bq_off[k * kBucketSub + j] = (int)c_run + part;
+                if (kBucketSub > 1) part += b.bcount[k * kBucketSub + j];
+            }
         }
         if (range && c > 0) {
             Tile tl;
@@ -518,6 +526,7 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
     } else {
         for (int r = 0; r < hi - lo; ++r) place(r);
     }
+    if (!publish) return;
     ev = wave_sum_u64(ev);
     if (lane_id() == 0 && ev) atomicAdd(&b.ctr->n_eval, ev);
     if (threadIdx.x == 0) {
@@ -531,15 +540,18 @@ __global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex
     }
 }
 
-// One thread per query segment with candidates: place it at its bucket's
-// offset plus the rank the histogram gave it (the kernels after this read
-// its record and cube through perm).
-__global__ void k_scatter(DevBatch b) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kScanBlock) void k_bucket_scan(DevBatch b, DevIndex ix) {
+    bucket_scan_body(b, ix, nullptr, true);
+}
+
+// Query segment i with candidates goes to its bucket's offset (from bq_off,
+// or from `off` when given) plus the rank the histogram gave it (the kernels
+// after this read its record and ball through perm).
+__device__ __forceinline__ void scatter_one(const DevBatch &b, int i, const int *off) {
     if (i >= b.nq) return;
     int k = b.key[i];
     if (k < 0) return;
-    int pos = b.bq_off[k * kBucketSub + (i % kBucketSub)] + b.qrank[i];
+    int pos = (off ? off[k] : b.bq_off[k * kBucketSub + (i % kBucketSub)]) + b.qrank[i];
     if (b.skey) {  // sorted tilings: the order key, for the bin sort
         b.skey[pos] = start_bits(b.rec[i].t0);
         b.sidx[pos] = i;
@@ -548,6 +560,22 @@ __global__ void k_scatter(DevBatch b) {
     b.perm[pos] = i;
     b.first_s[pos] = b.first[i];
     b.last_s[pos] = b.last[i];
+}
+
+__global__ void k_scatter(DevBatch b) { scatter_one(b, blockIdx.x * blockDim.x + threadIdx.x, nullptr); }
+
+// The bucket scan and the scatter in one launch, when the bucket offsets fit
+// LDS: every workgroup scans the bucket counts itself into LDS (a few
+// thousand counts, read from L2), workgroup 0 also publishes the offsets,
+// tiles and counters, and then each workgroup places its own kScanBlock
+// query segments.
+constexpr int kScanScatterBuckets = 8192;
+__global__ __launch_bounds__(kScanBlock) void k_scan_scatter(DevBatch b, DevIndex ix) {
+    static_assert(kBucketSub == 1, "one offset per bucket in LDS");
+    extern __shared__ int s_off[];
+    bucket_scan_body(b, ix, s_off, blockIdx.x == 0);
+    __syncthreads();
+    scatter_one(b, blockIdx.x * kScanBlock + threadIdx.x, s_off);
 }
 
 // Periodic tiles (Sec. 6): one wave per tile of s consecutive query segments
@@ -631,8 +659,13 @@ hipError_t launch_prepare(const double *const *q, const double *d, DevBatch b, D
     const size_t lds = ix.nb <= kQprepLdsBins ? (size_t)ix.nb * 2 * sizeof(double) : 0;
     TDS_LAUNCH_EV(ev_start, nullptr, k_qprep, dim3(qgrid), dim3(blk), lds, st, q[0], q[1], q[2], q[3],
                   q[4], q[5], q[6], q[7], d, b, ix);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanBlock), 0, st, b, ix);
-    hipLaunchKernelGGL(k_scatter, dim3(qgrid), dim3(blk), 0, st, b);
+    if (b.nbuckets <= kScanScatterBuckets) {
+        hipLaunchKernelGGL(k_scan_scatter, dim3((b.nq + kScanBlock - 1) / kScanBlock), dim3(kScanBlock),
+                           (size_t)b.nbuckets * sizeof(int), st, b, ix);
+    } else {
+        hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanBlock), 0, st, b, ix);
+        hipLaunchKernelGGL(k_scatter, dim3(qgrid), dim3(blk), 0, st, b);
+    }
     TDS_LAUNCH_CHECK();
 }
 
@@ -1104,88 +1137,6 @@ __global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
     }
 }
 
-// One block: offsets of the hit slabs, the hit and selection totals, and
-// (when the pair kernel counted them) the overlapping pairs. Each thread
-// takes a contiguous run of slabs and of wave slabs; runs of up to kScanRun
-// are read with independent loads issued together (one memory latency for
-// the whole kernel), longer ones in a loop.
-constexpr int kScanRun = 8;
-
-// The final counters also go to `host_out` (pinned host memory that the host
-// reads after the stream is synchronized), which saves a copy on the stream.
-__global__ __launch_bounds__(kScanBlock) void k_hit_scan(Slabs sl, Counters *__restrict__ ctr,
-                                                         int count_ovl, Counters *host_out,
-                                                         NextClear next) {
-    // the next batch of this handle starts from cleared counters (its own
-    // Counters slot, and bucket counters no kernel of this batch reads now)
-    if (next.ctr) {
-        for (int k = threadIdx.x; k < next.nbuckets; k += kScanBlock) {
-            next.bcount[k] = 0;
-            next.bj2[k] = -1;
-        }
-        if (threadIdx.x == 0) *next.ctr = Counters{};
-    }
-    const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
-    const long long per = (nsl + kScanBlock - 1) / kScanBlock;
-    const long long lo = min(nsl, (long long)threadIdx.x * per), hi = min(nsl, lo + per);
-    const long long per_w = (sl.nwaves + kScanBlock - 1) / kScanBlock;
-    const long long wlo = min((long long)sl.nwaves, (long long)threadIdx.x * per_w);
-    const long long whi = min((long long)sl.nwaves, wlo + per_w);
-    long long sum = 0, sel = 0, ovl = 0;
-    const bool held = per <= kScanRun && per_w <= kScanRun;
-    int h[kScanRun];
-    if (held) {
-        int c[kScanRun];
-        unsigned long long o[kScanRun];
-#pragma unroll
-        for (int j = 0; j < kScanRun; ++j) {
-            h[j] = lo + j < hi ? sl.slab_h[lo + j] : 0;
-            c[j] = lo + j < hi ? sl.slab_n[lo + j] : 0;
-            o[j] = count_ovl && wlo + j < whi ? sl.wave_ovl[wlo + j] : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < kScanRun; ++j) {
-            sum += h[j];
-            sel += c[j];
-            ovl += (long long)o[j];
-        }
-    } else {
-        for (long long k = lo; k < hi; ++k) {
-            sum += sl.slab_h[k];
-            sel += sl.slab_n[k];
-        }
-        if (count_ovl)
-            for (long long k = wlo; k < whi; ++k) ovl += (long long)sl.wave_ovl[k];
-    }
-    // hit offsets, selected pairs and overlap counts in one pass of scans
-    const long long vals[4] = {sum, sel, ovl, 0};
-    long long runs[4], tots[4];
-    block_exclusive_scan4<kScanBlock>(vals, runs, tots);
-    long long run = runs[0];
-    if (held) {
-#pragma unroll
-        for (int j = 0; j < kScanRun; ++j)
-            if (lo + j < hi) {
-                sl.hit_off[lo + j] = run;
-                run += h[j];
-            }
-    } else {
-        for (long long k = lo; k < hi; ++k) {
-            sl.hit_off[k] = run;
-            run += sl.slab_h[k];
-        }
-    }
-    const long long tot = tots[0], sel_tot = tots[1], ovl_tot = tots[2];
-    if (threadIdx.x == 0) {
-        sl.hit_off[nsl] = tot;
-        ctr->hits = (unsigned long long)tot;
-        ctr->cand = (unsigned long long)sel_tot;
-        ctr->n_slabs = (unsigned long long)nsl;
-        if (count_ovl) ctr->overlap = (unsigned long long)ovl_tot;
-        if (host_out) *host_out = *ctr;
-    }
-}
-
 // Grid of a persistent launch: the blocks that are resident at once. On
 // MI355X a launch sized by the occupancy query leaves one wave per SIMD (per
 // CU: 4 waves) without a slot, measured with per-wave start stamps: that many
@@ -1289,16 +1240,14 @@ hipError_t launch_pair(DevBatch b, DevIndex ix, int mode, int block, int grid, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, int count_ovl, hipStream_t st,
-                         hipEvent_t ev_stop, Counters *host_out, NextClear next) {
+hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, hipStream_t st, hipEvent_t ev_stop) {
     if (b.nq == 0) {
         if (ev_stop) (void)hipEventRecord(ev_stop, st);
         return hipGetLastError();
     }
     static const int grid = resident_blocks(k_refine, 256);
-    hipLaunchKernelGGL(k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix, b.ctr);
-    TDS_LAUNCH_EV(nullptr, ev_stop, k_hit_scan, dim3(1), dim3(kScanBlock), 0, st, sl, b.ctr,
-                  count_ovl, host_out, next);
+    TDS_LAUNCH_EV(nullptr, ev_stop, k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix,
+                  b.ctr);
     TDS_LAUNCH_CHECK();
 }
 
@@ -1319,36 +1268,119 @@ hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st) {
     TDS_LAUNCH_CHECK();
 }
 
-// --------------------------------------------------------------- translate
-// One wave per hit slab: its hits go to their dense positions (the slab's
-// offset plus rank), the first n of them as caller-index records.
-__global__ __launch_bounds__(256) void k_translate(Slabs sl, const Counters *__restrict__ ctr,
-                                                   int64_t n, const int32_t *__restrict__ perm,
-                                                   DevIndex ix, int64_t *out) {
-    const int lane = threadIdx.x & 63;
-    const long long nsl = (long long)ctr->n_slabs;
-    const long long nw = (long long)gridDim.x * 4;
-    const long long lim = min((long long)n, (long long)ctr->hits);  // n: the caller's capacity
-    for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
-        const long long k = sl.hit_off[s] + lane;
-        if (lane < sl.slab_h[s] && k < lim) {
-            const Hit24 h = sl.hits[s * kSlab + lane];
-            int64_t *o = out + 5 * k;
-            o[0] = perm[h.q];
-            o[1] = ix.orig[h.e];
-            o[2] = ix.traj[h.e];
-            o[3] = __double_as_longlong(h.ta);
-            o[4] = __double_as_longlong(h.tb);
+// The batch's last kernel, enqueued when the caller fetches: the position of
+// each hit slab's hits in the dense output (hit_off), the records of the
+// first n hits in caller indices, and the final counters. Workgroup g takes
+// a contiguous run of slabs; its hits follow those of every earlier slab,
+// which it sums itself (each workgroup reads the hit counts before its run:
+// few workgroups, a few thousand counts, read with independent loads), so
+// no second pass or inter-workgroup wait is needed. The run goes in rounds
+// of kEmitBlock slabs: a workgroup scan gives the slabs' offsets, then each
+// thread takes hits of the round (a search over the round's offsets in LDS
+// finds a hit's slab), so the loads of all hits are in flight together.
+// Workgroup 0 also sums hits, selections and (when the pair kernel counted
+// them) overlapping pairs over the whole batch, publishes the counters (also
+// to `host_out`, pinned host memory that the host reads after the stream is
+// synchronized, which saves a copy on the stream) and clears the counters of
+// the handle's next batch (its own Counters slot, and bucket counters no
+// kernel of this batch reads). Running it again (another output buffer)
+// gives the same offsets and counters.
+constexpr int kEmitBlock = 256;
+constexpr int kEmitGrid = 64;
+constexpr int kEmitIlp = 4;  // independent loads per thread in the sums
+
+// Sum of v[k] over k in [lo, hi) by the workgroup (every thread gets it).
+template <class T>
+__device__ __forceinline__ long long emit_sum(const T *__restrict__ v, long long lo, long long hi,
+                                              long long *s_red) {
+    long long acc[kEmitIlp] = {};
+    long long k = lo + threadIdx.x;
+    for (; k + (kEmitIlp - 1) * kEmitBlock < hi; k += kEmitIlp * kEmitBlock) {
+#pragma unroll
+        for (int j = 0; j < kEmitIlp; ++j) acc[j] += (long long)v[k + j * kEmitBlock];
+    }
+    for (; k < hi; k += kEmitBlock) acc[0] += (long long)v[k];
+    long long t = 0;
+#pragma unroll
+    for (int j = 0; j < kEmitIlp; ++j) t += acc[j];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    __syncthreads();  // s_red is free again
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    long long r = 0;
+#pragma unroll
+    for (int w = 0; w < kEmitBlock / 64; ++w) r += s_red[w];
+    return r;
+}
+
+__global__ __launch_bounds__(kEmitBlock) void k_emit(Slabs sl, Counters *__restrict__ ctr, int64_t n,
+                                                     const int32_t *__restrict__ perm, DevIndex ix,
+                                                     int64_t *out, int count_ovl, Counters *host_out,
+                                                     NextClear next) {
+    __shared__ long long s_red[kEmitBlock / 64];
+    __shared__ int s_loc[kEmitBlock + 1];  // round-local exclusive offsets, then the total
+    const int tid = threadIdx.x;
+    const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
+    const long long per = (nsl + gridDim.x - 1) / gridDim.x;
+    const long long lo = min(nsl, (long long)blockIdx.x * per), hi = min(nsl, lo + per);
+    long long pre = emit_sum(sl.slab_h, 0, lo, s_red);
+    for (long long base = lo; base < hi; base += kEmitBlock) {
+        const long long k = base + tid;
+        const int h = k < hi ? sl.slab_h[k] : 0;
+        const long long vals[4] = {h, 0, 0, 0};
+        long long runs[4], tots[4];
+        block_exclusive_scan4<kEmitBlock>(vals, runs, tots);
+        s_loc[tid] = (int)runs[0];
+        if (tid == 0) s_loc[kEmitBlock] = (int)tots[0];
+        if (k < hi) sl.hit_off[k] = pre + runs[0];
+        __syncthreads();
+        const int cnt = (int)min((long long)kEmitBlock, hi - base);
+        const int rh = s_loc[kEmitBlock];
+        // hits of the round in output order; hit r lies in the last slab j
+        // of the round with s_loc[j] <= r
+        for (int r = tid; r < rh && pre + r < n; r += kEmitBlock) {
+            int a = 0, z = cnt - 1;
+            while (a < z) {
+                const int m = (a + z + 1) >> 1;
+                if (s_loc[m] <= r) a = m; else z = m - 1;
+            }
+            const Hit24 hh = sl.hits[(base + a) * kSlab + (r - s_loc[a])];
+            int64_t *o = out + 5 * (pre + r);
+            o[0] = perm[hh.q];
+            o[1] = ix.orig[hh.e];
+            o[2] = ix.traj[hh.e];
+            o[3] = __double_as_longlong(hh.ta);
+            o[4] = __double_as_longlong(hh.tb);
         }
+        pre += tots[0];
+        __syncthreads();  // s_loc is rewritten by the next round
+    }
+    if (blockIdx.x != 0) return;
+    if (next.ctr) {
+        for (int k = tid; k < next.nbuckets; k += kEmitBlock) {
+            next.bcount[k] = 0;
+            next.bj2[k] = -1;
+        }
+        if (tid == 0) *next.ctr = Counters{};
+    }
+    const long long sh = emit_sum(sl.slab_h, 0, nsl, s_red);
+    const long long sn = emit_sum(sl.slab_n, 0, nsl, s_red);
+    const long long so = count_ovl ? emit_sum(sl.wave_ovl, 0, sl.nwaves, s_red) : 0;
+    if (tid == 0) {
+        ctr->hits = (unsigned long long)sh;
+        ctr->cand = (unsigned long long)sn;
+        ctr->n_slabs = (unsigned long long)nsl;
+        if (count_ovl) ctr->overlap = (unsigned long long)so;
+        if (host_out) *host_out = *ctr;
     }
 }
 
-hipError_t launch_translate(Slabs sl, const Counters *ctr, int64_t n, const int32_t *perm,
-                            DevIndex ix, void *out_hits, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    static const int grid = resident_blocks(k_translate, 256);
-    hipLaunchKernelGGL(k_translate, dim3(grid), dim3(256), 0, st, sl, ctr, n, perm, ix,
-                       (int64_t *)out_hits);
+hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, const int32_t *perm, DevIndex ix,
+                       void *out_hits, int count_ovl, Counters *host_out, NextClear next,
+                       hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+    TDS_LAUNCH_EV(ev_start, ev_stop, k_emit, dim3(kEmitGrid), dim3(kEmitBlock), 0, st, sl, ctr,
+                  out_hits ? n : (int64_t)0, perm, ix, (int64_t *)out_hits, count_ovl, host_out,
+                  next);
     TDS_LAUNCH_CHECK();
 }
 
