@@ -736,9 +736,8 @@ static int enqueue_emit(tds_query *q, void *out, int64_t n) {
     if (q->b.nq > 0) {
         const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0 && out;
         const int kovl = (q->opts.flags & TDS_QF_KERNEL_OVERLAP) ? 1 : 0;
-        HIP_TRY(launch_emit(q->sl, q->b.ctr, n, q->b.perm, q->ix->dev, out, kovl, q->host_ctr,
-                            q->next, q->stream, timing ? q->ev[4] : nullptr,
-                            timing ? q->ev[5] : nullptr));
+        HIP_TRY(launch_emit(q->sl, q->b.ctr, n, q->ix->dev, out, kovl, q->host_ctr, q->next,
+                            q->stream, timing ? q->ev[4] : nullptr, timing ? q->ev[5] : nullptr));
     }
     q->emitted = true;
     return TDS_OK;
@@ -1154,7 +1153,7 @@ int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj
     HIP_TRY(q->tr_out.ensure(nn * sizeof(tds_traj_hit) + sizeof(long long)));
     tds_traj_hit *recs = q->tr_out.as<tds_traj_hit>();
     long long *total_dev = reinterpret_cast<long long *>(recs + nn);
-    HIP_TRY(launch_traj_merge(q->sl, q->b.ctr, n, q->b.perm, qt, q->ix->dev, t, q->tr_temp.p,
+    HIP_TRY(launch_traj_merge(q->sl, q->b.ctr, n, qt, q->ix->dev, t, q->tr_temp.p,
                               q->tr_temp.bytes, recs, total_dev, st));
     // the record count to pinned host memory (after the handle's counters)
     long long *host_total = reinterpret_cast<long long *>(reinterpret_cast<char *>(q->host_ctr) + sizeof(Counters));
@@ -1332,8 +1331,8 @@ int tds_search_noalloc(const tds_index *ix, const tds_segments *qs, const double
         HIP_TRY(launch_pair(b, ix->dev, o.mode, o.block_size, o.grid, kovl, sl, st));
         HIP_TRY(launch_refine(b, ix->dev, sl, st));
         // offsets, counters and the first cap records in one kernel
-        HIP_TRY(launch_emit(sl, b.ctr, cap, b.perm, ix->dev, cap > 0 ? (void *)out : nullptr, kovl,
-                            nullptr, NextClear{}, st));
+        HIP_TRY(launch_emit(sl, b.ctr, cap, ix->dev, cap > 0 ? (void *)out : nullptr, kovl, nullptr,
+                            NextClear{}, st));
     }
     Counters ctr{};
     HIP_TRY(hipMemcpyAsync(&ctr, b.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));

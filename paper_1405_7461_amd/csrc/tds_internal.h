@@ -168,12 +168,14 @@ __host__ __device__ inline long long tile_cost(int nq, int nchunk, int pass_cost
     return (long long)nchunk * ((long long)nq + pass_overhead(nq, pass_cost, stage_cost));
 }
 
-// A pair selected by the pair kernel (sorted query / sorted entry positions).
+// A pair selected by the pair kernel: the query segment's caller index and
+// the entry's sorted position.
 struct Cand {
     uint32_t q, e;
 };
 
-// Device result record: positions in sorted query / sorted entry order.
+// Device result record: the query segment's caller index, the entry's
+// sorted position, the interval.
 struct Hit24 {
     uint32_t q, e;
     double ta, tb;
@@ -399,9 +401,9 @@ hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, hipStream_t st,
 // The batch's last kernel: hit offsets, the dense caller-index records of the
 // first n hits (none when out_hits is null), the final counters (also to
 // host_out when not null) and the clearing of the next batch's counters.
-hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, const int32_t *perm, DevIndex ix,
-                       void *out_hits, int count_ovl, Counters *host_out, NextClear next,
-                       hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, DevIndex ix, void *out_hits,
+                       int count_ovl, Counters *host_out, NextClear next, hipStream_t st,
+                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st);
 // Trajectory merge (tds_traj.hip): temp bytes for n hits, and the launch
 // (n > 0 hits; writes the merged records to `out` and their number to *total).
@@ -416,8 +418,8 @@ hipError_t launch_periodic(DevBatch b, DevIndex ix, hipStream_t st);
 // batch chain and the tiles, and scans the work units.
 hipError_t launch_greedy(DevBatch b, GreedyBufs g, DevIndex ix, int bound, int is_max,
                          hipStream_t st);
-hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
-                             const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,
+hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int64_t *qtraj,
+                             DevIndex ix, TrajBufs t, void *temp,
                              size_t temp_bytes, tds_traj_hit *out, long long *total,
                              hipStream_t st);
 int chunk_for(int mode, int block);

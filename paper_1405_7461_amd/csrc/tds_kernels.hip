@@ -923,13 +923,16 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                     // positions past the placed segments hold no index, so
                     // the read-ahead clamps it.
                     auto clampq = [&](int i) { return min(max(i, 0), nq - 1); };
-                    QRec64 qn = rec[clampq(perm[qb])];
+                    int pcur = perm[qb];  // caller index of query qs
+                    QRec64 qn = rec[clampq(pcur)];
                     int pnext = perm[qb + 1];
                     for (int qs = qb; qs < qe; ++qs) {
                         const QRec64 q = qn;
+                        const int pq = pcur;
                         const int pn = pnext;
                         pnext = perm[qs + 2];
                         qn = rec[clampq(pn)];
+                        pcur = pn;
                         progress(1);
 #pragma unroll
                         for (int j = 0; j < EPT; ++j) {
@@ -937,7 +940,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                             const Pair64 p = decide64(q, et0[j], et1[j], ex0[j], ey0[j], ez0[j],
                                                       evx[j], evy[j], evz[j]);
                             if (COUNT_OVL) ovl_acc += __popcll(__ballot(p.tlo < p.thi));
-                            select(p.hit, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                            select(p.hit, Cand{(uint32_t)pq, (uint32_t)(wb + j * 64 + lane)});
                         }
                     }
                 };
@@ -992,11 +995,12 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 // in registers would cost occupancy).
                 auto emit = [&](const float4 &qv, const int qs, auto full) {
                     constexpr bool FULL = decltype(full)::value;
+                    const uint32_t qc = (uint32_t)perm[qs];  // caller index
 #pragma unroll
                     for (int j = 0; j < EPT; ++j) {
                         const bool has = FULL || j < nv;  // wave-uniform
                         const float g = has ? dot_of(ec[j], qv) : NAN;
-                        select(g <= qv.x, Cand{(uint32_t)qs, (uint32_t)(wb + j * 64 + lane)});
+                        select(g <= qv.x, Cand{qc, (uint32_t)(wb + j * 64 + lane)});
                     }
                 };
                 auto count_ovl = [&](const int qs) {
@@ -1015,12 +1019,13 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
                 // ball's threshold against this chunk, evaluated in binary64
                 // with margins for its own rounding and rounded up:
                 //   T = (r + H)^2 - |C|^2 + kDotSlack (E2 + |C|^2);
-                // then it walks them four at a time with broadcast LDS reads
-                // at fixed offsets: the four smallest s are computed before
-                // the one (rarely taken) branch, which gives the scheduler
-                // four independent chains. LDS requests of one wave complete
-                // in order, so the slice is rewritten only after the previous
-                // walk has read it.
+                // then it walks them kGroup at a time with broadcast LDS
+                // reads at fixed offsets: the kGroup smallest s (each the
+                // minimum over the lane's EPT entries) are computed before the
+                // one (rarely taken) branch, which gives the scheduler
+                // kGroup x EPT independent chains. LDS requests of one wave
+                // complete in order, so the slice is rewritten only after the
+                // previous walk has read it.
                 __shared__ float4 s_q[BLOCK / 64][kStage];
                 const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
                 auto walk = [&](auto full) {
@@ -1105,19 +1110,20 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
 // pair of the binary32 filter may be a miss) and, for hits, the interval.
 // One wave per slab (grid-stride); the hits of slab s are compacted to the
 // front of hit slab s with a ballot, so no atomics are needed.
-__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec,
-                                                const int32_t *__restrict__ perm, Slabs sl,
+__global__ __launch_bounds__(256) void k_refine(const QRec64 *__restrict__ rec, Slabs sl,
                                                 DevIndex ix, const Counters *__restrict__ ctr) {
     const int lane = threadIdx.x & 63;
     const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
     const long long nw = (long long)gridDim.x * 4;
     for (long long s = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); s < nsl; s += nw) {
+        // the count and the records are read together (a slab's memory
+        // exists whatever its count; records past it are not used)
         const int cnt = sl.slab_n[s];
+        const Cand c = sl.cand[s * kSlab + lane];
         bool hit = false;
         Hit24 h;
         if (lane < cnt) {
-            const Cand c = sl.cand[s * kSlab + lane];
-            const QRec64 q = rec[perm[c.q]];
+            const QRec64 q = rec[c.q];
             const int e = (int)c.e;
             const Pair64 p = decide64(q, ix.t0[e], ix.t1[e], ix.x0[e], ix.y0[e], ix.z0[e], ix.vx[e],
                                       ix.vy[e], ix.vz[e]);
@@ -1246,8 +1252,7 @@ hipError_t launch_refine(DevBatch b, DevIndex ix, Slabs sl, hipStream_t st, hipE
         return hipGetLastError();
     }
     static const int grid = resident_blocks(k_refine, 256);
-    TDS_LAUNCH_EV(nullptr, ev_stop, k_refine, dim3(grid), dim3(256), 0, st, b.rec, b.perm, sl, ix,
-                  b.ctr);
+    TDS_LAUNCH_EV(nullptr, ev_stop, k_refine, dim3(grid), dim3(256), 0, st, b.rec, sl, ix, b.ctr);
     TDS_LAUNCH_CHECK();
 }
 
@@ -1314,9 +1319,8 @@ __device__ __forceinline__ long long emit_sum(const T *__restrict__ v, long long
 }
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit(Slabs sl, Counters *__restrict__ ctr, int64_t n,
-                                                     const int32_t *__restrict__ perm, DevIndex ix,
-                                                     int64_t *out, int count_ovl, Counters *host_out,
-                                                     NextClear next) {
+                                                     DevIndex ix, int64_t *out, int count_ovl,
+                                                     Counters *host_out, NextClear next) {
     __shared__ long long s_red[kEmitBlock / 64];
     __shared__ int s_loc[kEmitBlock + 1];  // round-local exclusive offsets, then the total
     const int tid = threadIdx.x;
@@ -1346,7 +1350,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(Slabs sl, Counters *__restr
             }
             const Hit24 hh = sl.hits[(base + a) * kSlab + (r - s_loc[a])];
             int64_t *o = out + 5 * (pre + r);
-            o[0] = perm[hh.q];
+            o[0] = hh.q;
             o[1] = ix.orig[hh.e];
             o[2] = ix.traj[hh.e];
             o[3] = __double_as_longlong(hh.ta);
@@ -1375,12 +1379,11 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(Slabs sl, Counters *__restr
     }
 }
 
-hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, const int32_t *perm, DevIndex ix,
-                       void *out_hits, int count_ovl, Counters *host_out, NextClear next,
-                       hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, DevIndex ix, void *out_hits,
+                       int count_ovl, Counters *host_out, NextClear next, hipStream_t st,
+                       hipEvent_t ev_start, hipEvent_t ev_stop) {
     TDS_LAUNCH_EV(ev_start, ev_stop, k_emit, dim3(kEmitGrid), dim3(kEmitBlock), 0, st, sl, ctr,
-                  out_hits ? n : (int64_t)0, perm, ix, (int64_t *)out_hits, count_ovl, host_out,
-                  next);
+                  out_hits ? n : (int64_t)0, ix, (int64_t *)out_hits, count_ovl, host_out, next);
     TDS_LAUNCH_CHECK();
 }
 

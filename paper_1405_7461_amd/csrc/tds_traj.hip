@@ -38,7 +38,6 @@ __device__ __forceinline__ unsigned long long order_bits(long long x) {
 
 // One wave per hit slab: dense hit k gets its trajectories and interval.
 __global__ __launch_bounds__(256) void k_traj_gather(Slabs sl, const Counters *__restrict__ ctr,
-                                                     const int32_t *__restrict__ perm,
                                                      const int64_t *__restrict__ qtraj_in,
                                                      DevIndex ix, TrajBufs t) {
     const int lane = threadIdx.x & 63;
@@ -48,7 +47,7 @@ __global__ __launch_bounds__(256) void k_traj_gather(Slabs sl, const Counters *_
         if (lane < sl.slab_h[s]) {
             const long long k = sl.hit_off[s] + lane;
             const Hit24 h = sl.hits[s * kSlab + lane];
-            t.qt[k] = qtraj_in[perm[h.q]];
+            t.qt[k] = qtraj_in[h.q];
             t.et[k] = ix.traj[h.e];
             t.ta[k] = h.ta;
             t.tb[k] = h.tb;
@@ -356,8 +355,8 @@ size_t traj_temp_bytes(long long n) {
     return most;
 }
 
-hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int32_t *perm,
-                             const int64_t *qtraj, DevIndex ix, TrajBufs t, void *temp,
+hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const int64_t *qtraj,
+                             DevIndex ix, TrajBufs t, void *temp,
                              size_t temp_bytes, tds_traj_hit *out, long long *total,
                              hipStream_t st) {
     if (n <= 0) return hipErrorInvalidValue;  // the caller handles a batch without hits
@@ -366,7 +365,7 @@ hipError_t launch_traj_merge(Slabs sl, const Counters *ctr, long long n, const i
     const bool one = n <= kTrajOneSortMax;
     if (one && (!t.kin || !t.kout)) return hipErrorInvalidValue;
     if (!one) t.kin = t.kout = nullptr;
-    hipLaunchKernelGGL(k_traj_gather, dim3(1024), dim3(256), 0, st, sl, ctr, perm, qtraj, ix, t);
+    hipLaunchKernelGGL(k_traj_gather, dim3(1024), dim3(256), 0, st, sl, ctr, qtraj, ix, t);
     if (n <= kTrajRankMax) {
         const dim3 rg((unsigned)((n + kRankBlock - 1) / kRankBlock), (unsigned)((n + kRankTile - 1) / kRankTile));
         hipLaunchKernelGGL(k_traj_rank, rg, dim3(kRankBlock), 0, st, t, n);
