@@ -439,3 +439,41 @@ def test_handle_reuse_across_batches():
     finally:
         qh.close()
         ix.close()
+
+
+def _staggered(seg, seed):
+    """The segments with each trajectory's times shifted by its own offset in
+    [0, 1), so that start times spread over every bin of a fine bin table."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    off = rng.random(int(seg.traj.max()) + 1)
+    out = seg.subset(np.arange(len(seg)))
+    out.t0 = out.t0 + off[out.traj]
+    out.t1 = out.t1 + off[out.traj]
+    return out
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_bucket_offsets_in_and_beyond_lds(mode):
+    """Bucket counts whose offsets fit LDS are scanned inside the scatter
+    (every workgroup scans them itself); more buckets take the separate
+    one-workgroup scan and scatter. Range tiling with 1,500 non-empty bins
+    (6,000 buckets) and with 3,000 (12,000), Periodic with m = 3,000 and
+    10,000 (m buckets): every result equals the oracle."""
+    db = _staggered(gen.make_db("C2", ntraj=120), 41)
+    q = db.subset(np.flatnonzero(db.traj < 12))  # 12 trajectories moved by 0.5 in x
+    q.x0 = q.x0 + 0.5
+    q.x1 = q.x1 + 0.5
+    q = q.with_d(2.0)
+    want = oracle.search(db, q)
+    assert len(want) >= len(q)
+    for m, tiling in ((1500, "range"), (3000, "range"), (3000, "periodic"), (10000, "periodic")):
+        ix = tds.build_index(db, m)
+        try:
+            nb = ix.info()["nonempty_bins"]
+            say(f"buckets {mode} {tiling} m={m}: {nb} non-empty bins")
+            if tiling == "range":
+                assert nb * 4 > 8192 if m == 3000 else nb * 4 <= 8192
+            got, st, _ = run(db, q, m, index=ix, mode=mode, tiling=tiling, batch_size=64)
+            compare(got, want, db, f"{tiling} m={m}")
+        finally:
+            ix.close()
