@@ -528,7 +528,8 @@ def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4,
                     batches=int(st["batches"]), retries=int(st["retries"]),
                     mean_batch_requests=float(np.mean([x["n_batch_requests"] for x in infos])),
                     hits=int(sum(x["n_hit"] for x in infos)), busy_s=float(st["busy_s"]),
-                    device_bytes=int(st["device_bytes"]))
+                    stage_s=float(st["stage_s"]), wait_s=float(st["wait_s"]),
+                    split_s=float(st["split_s"]), device_bytes=int(st["device_bytes"]))
 
     sat = serve(np.zeros(n_requests), warm=True)
     sat_rate = n_requests / sat["wall_s"]
@@ -560,7 +561,9 @@ def serving_form(log_fn=log, n_requests=6000, rates=(0.5, 0.8, 0.95), streams=4,
                 build_s=round(build_s, 2),
                 saturation_req_s=sat_rate, saturation_pair_tests_s=float(n_ovl.sum() / sat["wall_s"]),
                 saturation_p50_ms=sat["p50_ms"], saturation_batches=sat["batches"],
-                saturation_busy_s=sat["busy_s"], device_bytes=sat["device_bytes"],
+                saturation_busy_s=sat["busy_s"],
+                saturation_busy_parts_s=dict(stage=sat["stage_s"], wait=sat["wait_s"], split=sat["split_s"]),
+                device_bytes=sat["device_bytes"],
                 kernel_batch=dict(requests=80, segments=len(big), ms_per_step=kb["ms_per_step"],
                                   pair_tests_s=kb["value"]),
                 rates=runs)

@@ -449,6 +449,10 @@ typedef struct {
     int64_t batches, requests_done, retries, segments;
     int64_t device_bytes;  /* executors' device bytes now */
     double busy_s;         /* executor time spent in batches, summed over executors */
+    /* the parts of busy_s: copying requests into pinned staging and enqueueing the
+       upload and the batch; waiting for the batch and its results (tds_fetch_results);
+       splitting the results per request and updating alpha */
+    double stage_s, wait_s, split_s;
 } tds_server_stats;
 
 typedef struct tds_server tds_server;

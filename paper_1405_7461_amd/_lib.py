@@ -103,7 +103,8 @@ class tds_request_info(C.Structure):
 
 class tds_server_stats(C.Structure):
     _fields_ = [("batches", C.c_int64), ("requests_done", C.c_int64), ("retries", C.c_int64),
-                ("segments", C.c_int64), ("device_bytes", C.c_int64), ("busy_s", C.c_double)]
+                ("segments", C.c_int64), ("device_bytes", C.c_int64), ("busy_s", C.c_double),
+                ("stage_s", C.c_double), ("wait_s", C.c_double), ("split_s", C.c_double)]
 
 
 # name -> (restype, argtypes); every symbol include/tds.h declares

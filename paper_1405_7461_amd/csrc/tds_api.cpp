@@ -1033,16 +1033,25 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
     if (!q->pending && !q->fetched) return fail(TDS_ESTATE, "tds_fetch_results: no batch");
     hipStream_t st = q->stream;
     const bool timing = (q->opts.flags & TDS_QF_TIMING) != 0;
+    // Host output in pinned memory (hipHostMalloc) is written by the kernel
+    // directly; other host output is staged on the device and copied.
+    void *direct = nullptr;
+    if (out_mem == TDS_MEM_HOST && cap > 0) {
+        hipPointerAttribute_t a{};
+        if (hipPointerGetAttributes(&a, out) == hipSuccess && a.type == hipMemoryTypeHost)
+            direct = a.devicePointer ? a.devicePointer : (void *)out;
+        (void)hipGetLastError();  // pageable memory: the query fails, nothing is pending
+    }
+    void *dst = out_mem == TDS_MEM_DEVICE ? (void *)out : direct;  // written by the kernel
     // A pending batch: its last kernel (offsets, at most cap records, the
     // counters) is enqueued before the host waits, so the device does not
     // idle while the host wakes up. It runs again below if the batch had to
-    // be re-run. Host output is staged on the device first; the early run
-    // only uses staging that is already large enough (a generous cap
-    // allocates nothing before the count is known).
+    // be re-run. The early run only uses staging that is already large
+    // enough (a generous cap allocates nothing before the count is known).
     bool early = false;
     const bool stage_fits = (size_t)cap * sizeof(tds_hit) <= q->out_stage.bytes;
-    if (q->pending && cap > 0 && (out_mem == TDS_MEM_DEVICE || stage_fits)) {
-        int rc = enqueue_emit(q, out_mem == TDS_MEM_DEVICE ? (void *)out : q->out_stage.p, cap);
+    if (q->pending && cap > 0 && (dst || stage_fits)) {
+        int rc = enqueue_emit(q, dst ? dst : q->out_stage.p, cap);
         if (rc) return rc;
         early = true;
     }
@@ -1054,15 +1063,19 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
     *n_total = n;
     const int64_t m = std::min<int64_t>(cap, n);
     if (m > 0) {
-        if (!early || q->stats.retries > 0) {  // the records now
-            if (out_mem == TDS_MEM_HOST) HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
-            int rc = enqueue_emit(q, out_mem == TDS_MEM_DEVICE ? (void *)out : q->out_stage.p, m);
+        const bool again = !early || q->stats.retries > 0;
+        if (again) {  // the records now
+            if (!dst) HIP_TRY(q->out_stage.ensure((size_t)m * sizeof(tds_hit)));
+            int rc = enqueue_emit(q, dst ? dst : q->out_stage.p, m);
             if (rc) return rc;
         }
         if (out_mem == TDS_MEM_HOST) {
-            HIP_TRY(hipMemcpyAsync(out, q->out_stage.p, (size_t)m * sizeof(tds_hit),
-                                   hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
+            if (!direct)
+                HIP_TRY(hipMemcpyAsync(out, q->out_stage.p, (size_t)m * sizeof(tds_hit),
+                                       hipMemcpyDeviceToHost, st));
+            // host output is complete on return (the early kernel finished
+            // before the wait for the batch)
+            if (!direct || again) HIP_TRY(hipStreamSynchronize(st));
         }
         // device output is ordered on the batch's stream (fetch timing is
         // read by tds_query_stats)

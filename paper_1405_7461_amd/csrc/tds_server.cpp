@@ -108,7 +108,7 @@ struct tds_server {
     bool failed = false;
     std::string fail_msg;
     int64_t n_finished = 0, n_batches = 0, n_retries = 0, n_segments = 0;
-    double busy_s = 0;
+    double busy_s = 0, stage_s = 0, wait_s = 0, split_s = 0;
     std::thread sched;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
@@ -239,6 +239,7 @@ void tds_server::finish(Batch &b, int32_t status) {
 }
 
 void tds_server::run_batch(Executor *e, Batch &b) {
+    const double t_start = now();
     const int64_t n = b.nseg;
     int rc = TDS_OK;
     auto fail_batch = [&](int code, const char *what) {
@@ -292,6 +293,7 @@ void tds_server::run_batch(Executor *e, Batch &b) {
     qo.capacity = std::max<int64_t>((int64_t)(o.k_safety * std::max(1.0, b.est_hits)), 1 << 16);
     rc = tds_query_batch(e->qh, &seg, e->dev_in + (size_t)8 * n, &qo, e->stream);
     if (rc) return fail_batch(rc, "tds_query_batch");
+    const double t_enq = now();
     int64_t total = 0;
     rc = tds_fetch_results(e->qh, e->pin_out, e->pin_out_cap, TDS_MEM_HOST, &total);
     if (rc) return fail_batch(rc, "tds_fetch_results");
@@ -307,40 +309,39 @@ void tds_server::run_batch(Executor *e, Batch &b) {
         rc = tds_fetch_results(e->qh, e->pin_out, e->pin_out_cap, TDS_MEM_HOST, &total);
         if (rc) return fail_batch(rc, "tds_fetch_results");
     }
+    const double t_fetched = now();
     tds_stats st{};
     (void)tds_query_stats(e->qh, &st);
     int64_t dev_bytes = 0;
     (void)tds_query_device_bytes(e->qh, &dev_bytes);
 
-    // split per request: counting sort by the request of each hit's segment
+    // split per request: the request of each hit's segment by a search over
+    // the batch's segment offsets (work in the hits, not in the segments),
+    // then a counting sort that keeps each request's hits in their order
     const size_t nr = b.reqs.size();
-    std::vector<int32_t> req_of((size_t)n);
-    for (size_t i = 0; i < nr; ++i)
-        std::fill(req_of.begin() + off[i], req_of.begin() + off[i + 1], (int32_t)i);
+    std::vector<int32_t> hreq((size_t)total);
     std::vector<int64_t> cnt(nr, 0);
-    std::vector<double> seg_hits((size_t)n, 0.0);
     for (int64_t h = 0; h < total; ++h) {
         const int64_t qi = e->pin_out[h].query_idx;
-        ++cnt[req_of[qi]];
-        seg_hits[qi] += 1.0;
+        const int32_t ri = (int32_t)(std::upper_bound(off.begin(), off.end(), qi) - off.begin()) - 1;
+        hreq[(size_t)h] = ri;
+        ++cnt[ri];
     }
     for (size_t i = 0; i < nr; ++i) b.reqs[i]->hits.resize((size_t)cnt[i]);
     std::fill(cnt.begin(), cnt.end(), 0);
+    // per-epoch hit fraction of this batch -> alpha (running average): the
+    // requests' candidate counts per epoch were summed at submission
+    std::vector<double> ev(o.epochs, 0.0), hv(o.epochs, 0.0);
     for (int64_t h = 0; h < total; ++h) {
         tds_hit x = e->pin_out[h];
-        const int32_t ri = req_of[x.query_idx];
+        const int32_t ri = hreq[(size_t)h];
+        Request &r = *b.reqs[ri];
         x.query_idx -= off[ri];
-        b.reqs[ri]->hits[(size_t)cnt[ri]++] = x;
+        hv[r.seg_epoch[(size_t)x.query_idx]] += 1.0;
+        r.hits[(size_t)cnt[ri]++] = x;
     }
-    // per-epoch hit fraction of this batch -> alpha (running average)
-    std::vector<double> ev(o.epochs, 0.0), hv(o.epochs, 0.0);
-    for (size_t i = 0; i < nr; ++i) {
-        const Request &r = *b.reqs[i];
-        for (int64_t j = 0; j < r.n; ++j) {
-            ev[r.seg_epoch[j]] += r.seg_eval[j];
-            hv[r.seg_epoch[j]] += seg_hits[off[i] + j];
-        }
-    }
+    for (size_t i = 0; i < nr; ++i)
+        for (const auto &pe : b.reqs[i]->epoch_eval) ev[pe.first] += pe.second;
     {
         std::lock_guard<std::mutex> lk(mu);
         for (int32_t k = 0; k < o.epochs; ++k)
@@ -348,6 +349,9 @@ void tds_server::run_batch(Executor *e, Batch &b) {
         e->reserved = (double)dev_bytes;
         n_retries += st.retries;
         n_segments += n;
+        stage_s += t_enq - t_start;
+        wait_s += t_fetched - t_enq;
+        split_s += now() - t_fetched;
     }
     finish(b, TDS_OK);
 }
@@ -550,6 +554,9 @@ int tds_server_stats_get(const tds_server *s, tds_server_stats *out) {
     for (auto &e : m->ex) b += e->reserved;
     out->device_bytes = (int64_t)b;
     out->busy_s = m->busy_s;
+    out->stage_s = m->stage_s;
+    out->wait_s = m->wait_s;
+    out->split_s = m->split_s;
     return TDS_OK;
 }
 

@@ -200,7 +200,7 @@ def test_server_and_reserve_arguments():
     lib = L.lib()
     assert C.sizeof(L.tds_server_opts) == 48 + C.sizeof(L.tds_query_opts)
     assert C.sizeof(L.tds_request_info) == 48
-    assert C.sizeof(L.tds_server_stats) == 48
+    assert C.sizeof(L.tds_server_stats) == 72
     opts = L.tds_query_opts(L.TDS_MODE_FP64, L.TDS_TILE_RANGE, 0, 0, 0, -1, 0, 0, 0)
     assert lib.tds_query_reserve(None, 10, 10, C.byref(opts)) == L.TDS_EINVAL
     assert b"tds_query_reserve" in lib.tds_last_error()
