@@ -1277,9 +1277,9 @@ hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st) {
 // each hit slab's hits in the dense output (hit_off), the records of the
 // first n hits in caller indices, and the final counters. Workgroup g takes
 // a contiguous run of slabs; its hits follow those of every earlier slab,
-// which it sums itself (each workgroup reads the hit counts before its run:
-// few workgroups, a few thousand counts, read with independent loads), so
-// no second pass or inter-workgroup wait is needed. The run goes in rounds
+// which it sums itself (each workgroup reads the hit counts before its run,
+// a few thousand counts from L2 with independent loads), so no second pass
+// or inter-workgroup wait is needed. The run goes in rounds
 // of kEmitBlock slabs: a workgroup scan gives the slabs' offsets, then each
 // thread takes hits of the round (a search over the round's offsets in LDS
 // finds a hit's slab), so the loads of all hits are in flight together.
@@ -1291,7 +1291,8 @@ hipError_t launch_reset_counters(Counters *c, int all, hipStream_t st) {
 // kernel of this batch reads). Running it again (another output buffer)
 // gives the same offsets and counters.
 constexpr int kEmitBlock = 256;
-constexpr int kEmitGrid = 64;
+constexpr int kEmitMinGroups = 64;
+constexpr int kEmitSpillPerGroup = 8;
 constexpr int kEmitIlp = 4;  // independent loads per thread in the sums
 
 // Sum of v[k] over k in [lo, hi) by the workgroup (every thread gets it).
@@ -1324,8 +1325,13 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(Slabs sl, Counters *__restr
     __shared__ long long s_red[kEmitBlock / 64];
     __shared__ int s_loc[kEmitBlock + 1];  // round-local exclusive offsets, then the total
     const int tid = threadIdx.x;
-    const long long nsl = sl.nwaves + min((long long)ctr->spill, sl.nslabs - sl.nwaves);
-    const long long per = (nsl + gridDim.x - 1) / gridDim.x;
+    const long long spill = min((long long)ctr->spill, sl.nslabs - sl.nwaves);
+    const long long nsl = sl.nwaves + spill;
+    // workgroups in use: kEmitMinGroups, and more as the selections spill
+    // beyond the wave slabs (batches with many hits); the rest return
+    const long long groups = min((long long)gridDim.x, kEmitMinGroups + spill / kEmitSpillPerGroup);
+    if ((long long)blockIdx.x >= groups) return;
+    const long long per = (nsl + groups - 1) / groups;
     const long long lo = min(nsl, (long long)blockIdx.x * per), hi = min(nsl, lo + per);
     long long pre = emit_sum(sl.slab_h, 0, lo, s_red);
     for (long long base = lo; base < hi; base += kEmitBlock) {
@@ -1382,7 +1388,11 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(Slabs sl, Counters *__restr
 hipError_t launch_emit(Slabs sl, Counters *ctr, int64_t n, DevIndex ix, void *out_hits,
                        int count_ovl, Counters *host_out, NextClear next, hipStream_t st,
                        hipEvent_t ev_start, hipEvent_t ev_stop) {
-    TDS_LAUNCH_EV(ev_start, ev_stop, k_emit, dim3(kEmitGrid), dim3(kEmitBlock), 0, st, sl, ctr,
+    // up to as many workgroups as are resident at once: batches with many
+    // hits write them in parallel (the kernel uses 64 of them, plus one per
+    // 8 spill slabs)
+    static const int grid = resident_blocks(k_emit, kEmitBlock);
+    TDS_LAUNCH_EV(ev_start, ev_stop, k_emit, dim3(grid), dim3(kEmitBlock), 0, st, sl, ctr,
                   out_hits ? n : (int64_t)0, ix, (int64_t *)out_hits, count_ovl, host_out, next);
     TDS_LAUNCH_CHECK();
 }
