@@ -800,6 +800,17 @@ __device__ __forceinline__ void set_prio(int p) {
 constexpr int ept_for_mode(int mode) { return mode == kModeFP64 ? TDS_EPT64 : TDS_EPT32; }
 int chunk_for(int mode, int) { return 64 * ept_for_mode(mode); }
 
+// The binary64 walk reads a chunk's 64-byte entries once per work range
+// and the tile's 80-byte query records once per chunk pass: its entry loads
+// are marked non-temporal, so that the L2 keeps the query records rather
+// than the entry stream (binary64 traffic 1.49x -> 1.18x of the unique bytes
+// on the 5M-entry workload at unchanged time). The binary32 filter keeps
+// ordinary loads: its 20-byte entries are re-read by neighbouring tiles
+// from L2, and marking them non-temporal made it slower.
+__device__ __forceinline__ double stream_load(const double *p) {
+    return __builtin_nontemporal_load(p);
+}
+
 __device__ __forceinline__ long long rfl64(long long v) {
     unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
     unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
@@ -901,15 +912,15 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const QRec64 *__restrict__ rec,
 #pragma unroll
                 for (int j = 0; j < EPT; ++j) {
                     const int e = wb + j * 64 + lane;
-                    if (e < we) {
-                        et0[j] = ix.t0[e];
-                        et1[j] = ix.t1[e];
-                        ex0[j] = ix.x0[e];
-                        ey0[j] = ix.y0[e];
-                        ez0[j] = ix.z0[e];
-                        evx[j] = ix.vx[e];
-                        evy[j] = ix.vy[e];
-                        evz[j] = ix.vz[e];
+                    if (e < we) {  // streamed: read once per tile (see stream_load)
+                        et0[j] = stream_load(&ix.t0[e]);
+                        et1[j] = stream_load(&ix.t1[e]);
+                        ex0[j] = stream_load(&ix.x0[e]);
+                        ey0[j] = stream_load(&ix.y0[e]);
+                        ez0[j] = stream_load(&ix.z0[e]);
+                        evx[j] = stream_load(&ix.vx[e]);
+                        evy[j] = stream_load(&ix.vy[e]);
+                        evz[j] = stream_load(&ix.vz[e]);
                     } else {  // an empty span never overlaps
                         et0[j] = INFINITY;
                         et1[j] = -INFINITY;
