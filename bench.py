@@ -603,7 +603,7 @@ def valu_probe(log_fn=log):
              "v_pk_max_u16", "v_max_f32_e64_abs", "v_pk_add_f16", "v_min_f32", "v_cmp_le_f32",
              "v_fma_f32", "v_fmac_f32", "v_mul_f32", "v_add_f32", "v_or_b32", "v_or3_b32", "v_max_f32",
              "v_sub_f32_e64_abs", "v_fma_f32_sgpr", "v_fmac_f32_sgpr", "v_fma_f32_3banks",
-             "v_fma_f32_same_bank")
+             "v_fma_f32_same_bank", "v_mfma_f32_16x16x4_f32", "v_mfma_f32_32x32x2_f32")
     for kind, name in enumerate(names):
         best = None
         for _ in range(3):

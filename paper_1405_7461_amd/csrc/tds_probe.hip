@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace {
 
 constexpr int kChains = 8;
@@ -110,6 +112,27 @@ __global__ __launch_bounds__(kBlock) void k_probe(int iters, float seed, float *
                         : "v40", "v44", "v48", "v52", "v56", "v60", "v64", "v68");
         }
         acc = seed;
+    } else if constexpr (KIND == 23 || KIND == 24) {
+        // binary32 matrix-core products: 23 v_mfma_f32_16x16x4_f32, 24
+        // v_mfma_f32_32x32x2_f32, eight independent accumulations
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        typedef float v16f __attribute__((ext_vector_type(16)));
+        const float a = seed * 1e-7f + lane * 1e-9f, b = seed * 3e-7f;
+        using Acc = typename std::conditional<KIND == 23, v4f, v16f>::type;
+        Acc d[kChains];
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) d[k] = Acc{} + (float)k;
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) {
+                if constexpr (KIND == 23)
+                    d[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d[k], 0, 0, 0);
+                else
+                    d[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d[k], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) acc += d[k][0] + d[k][3];
     } else if constexpr (KIND == 3) {
         double a[kChains], b = 1.0 + seed * 1e-9, c = seed * 1e-12 + lane * 1e-15;
 #pragma unroll
@@ -149,7 +172,8 @@ extern "C" {
  * 18 v_sub_f32 with an absolute-value operand (VOP3 form), 19 v_fma_f32 and
  * 20 v_fmac_f32 with the multiplicand in a scalar register, 21 v_fma_f32 with
  * its three sources in three register banks, 22 v_fma_f32 with its two
- * multiplicands in one bank) with `blocks` workgroups of 256
+ * multiplicands in one bank, 23 v_mfma_f32_16x16x4_f32, 24
+ * v_mfma_f32_32x32x2_f32) with `blocks` workgroups of 256
  * threads, each lane running `iters` iterations of 8 independent chain
  * steps, on `stream`, and waits for it.
  * Writes: *ms the kernel's duration (HIP events), *wave_instr the vector
@@ -160,7 +184,7 @@ extern "C" {
  */
 int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, double *wave_instr,
                    double *clock_hz) {
-    if (kind < 0 || kind > 22 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
+    if (kind < 0 || kind > 24 || blocks < 1 || iters < 1 || !ms || !wave_instr || !clock_hz) return -1;
     hipStream_t s = (hipStream_t)stream;
     const int waves = blocks * (kBlock / 64);
     float *sink = nullptr;
@@ -197,7 +221,9 @@ int tds_probe_valu(int kind, int blocks, int iters, void *stream, double *ms, do
             case 19: err = run_kind<19>(blocks, iters, seed, sink, st, s); break;
             case 20: err = run_kind<20>(blocks, iters, seed, sink, st, s); break;
             case 21: err = run_kind<21>(blocks, iters, seed, sink, st, s); break;
-            default: err = run_kind<22>(blocks, iters, seed, sink, st, s); break;
+            case 22: err = run_kind<22>(blocks, iters, seed, sink, st, s); break;
+            case 23: err = run_kind<23>(blocks, iters, seed, sink, st, s); break;
+            default: err = run_kind<24>(blocks, iters, seed, sink, st, s); break;
             }
         }
         if (err == hipSuccess) err = hipEventRecord(e1, s);
