@@ -247,10 +247,11 @@ void tds_query_destroy(tds_query *qh);
  * Returns once the work is enqueued; inputs in device memory must stay valid
  * until tds_fetch_results returns. Inputs in host memory are copied first.
  * Errors: TDS_EINVAL for null pointers, n out of range, an unknown mode,
- * tiling or block size, or (host inputs) an invalid segment or threshold;
- * TDS_ESTATE when the previous batch of the handle was not fetched;
- * TDS_ENOMEM / TDS_EDEVICE for failed device calls. Invalid device-resident
- * segments are reported by tds_fetch_results.
+ * tiling or block size; TDS_ESTATE when the previous batch of the handle was
+ * not fetched; TDS_ENOMEM / TDS_EDEVICE for failed device calls. Invalid
+ * segments or thresholds (non-finite values, t_end <= t_start, d < 0), in
+ * host or device memory, are found by the preparation kernel and reported
+ * by tds_fetch_results as TDS_EINVAL.
  */
 int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
                     const tds_query_opts *opts, void *stream);
@@ -263,7 +264,11 @@ int tds_query_batch(tds_query *qh, const tds_segments *q, const double *d,
  * TDS_MEM_HOST, device memory for TDS_MEM_DEVICE). *n_total always receives
  * the number of hits, so cap = 0 sizes the buffer. Host output is complete on
  * return; device output is written on the batch's stream, so work on another
- * stream must wait for it.
+ * stream must wait for it. Errors: TDS_EINVAL for bad arguments or a batch
+ * holding an invalid query segment or threshold; TDS_ESTATE without a
+ * pending or fetched batch; TDS_EOVERFLOW when the selections outgrow the
+ * buffer after max_retries regrowths; TDS_ENOMEM / TDS_EDEVICE for failed
+ * device calls.
  */
 int tds_fetch_results(tds_query *qh, tds_hit *out, int64_t cap, int32_t out_mem, int64_t *n_total);
 int tds_query_stats(const tds_query *qh, tds_stats *out);

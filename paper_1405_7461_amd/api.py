@@ -258,13 +258,21 @@ class Query:
     def fetch(self, out: str = "host", cap: Optional[int] = None) -> Hits:
         """Results of the last batch. The output buffer is sized from the
         previous batch's hit count, so one library call usually suffices; a
-        larger result is fetched again into a buffer of its size."""
+        larger result is fetched again into a buffer of its size.
+
+        out: "device" (CUDA tensors), "host" (numpy), or "pinned" (numpy
+        arrays over page-locked host memory, which the library's record
+        kernel writes directly: no staging copy)."""
         n = C.c_int64()
         rows = max(self._rows_hint, 1) if cap is None else max(int(cap), 1)
         if out == "device":
             import torch
             mk = lambda r: torch.empty((r, 5), dtype=torch.int64, device="cuda")
             ptr, mem = (lambda b: b.data_ptr()), L.TDS_MEM_DEVICE
+        elif out == "pinned":
+            import torch
+            mk = lambda r: torch.empty((r, 5), dtype=torch.int64, pin_memory=True).numpy()
+            ptr, mem = (lambda b: b.ctypes.data), L.TDS_MEM_HOST
         else:
             mk = lambda r: np.empty((r, 5), dtype=np.int64)
             ptr, mem = (lambda b: b.ctypes.data), L.TDS_MEM_HOST

@@ -15,7 +15,7 @@ arrays) and gamma = 1 - alpha - beta. T1..T3 and Theta are read off
 benchmark curves (time against interactions, one curve per candidate count
 c) by linear interpolation in i along the two curves that bracket c, then
 linearly in c. CPU component (Sec. 8.2): a fitted curve a + b q^e for the
-host work that scales with the query segments (validation and transfer of
+host work that scales with the query segments (the transfer of the
 host inputs) and sigma / bandwidth for returning sigma result bytes.
 
 Differences from the paper's setting: one call here is one persistent

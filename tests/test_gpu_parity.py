@@ -177,13 +177,17 @@ def test_overflow_retry():
     got, st, _ = run(db, q, 8, mode="fp32_refine", capacity=1, max_retries=2, out="device")
     compare(got, want, db, "retry device output")
     assert st["retries"] == 1
+    # page-locked host output, which the record kernel writes directly
+    got, st, _ = run(db, q, 8, mode="fp32_refine", capacity=1, max_retries=2, out="pinned")
+    compare(got, want, db, "retry page-locked output")
+    assert st["retries"] == 1
     # the same handle fetched repeatedly: its output buffer is sized from the
-    # previous batch, so the early translation covers every hit (host and
-    # device output)
+    # previous batch, so the early translation covers every hit (host,
+    # device and page-locked host output)
     ix = tds.build_index(db, 8)
     qh = tds.Query(ix)
     try:
-        for rep, out in enumerate(("host", "device", "host", "device")):
+        for rep, out in enumerate(("host", "device", "pinned", "host", "device", "pinned")):
             qh.batch(q, q.d, mode="fp32_refine", tiling="range")
             compare(qh.fetch(out=out).sorted(), want, db, f"repeated fetch {rep} {out}")
     finally:
