@@ -212,6 +212,10 @@ struct tds_query {
     long long traj_total = 0;
     tds_stats stats{};
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // recorded after the handle's own work for the host's waits, so that a
+    // wait does not also cover what other callers enqueue later on the same
+    // stream
+    hipEvent_t ev_wait = nullptr;
 };
 
 // Device scratch of tds_search_noalloc: every per-batch buffer of that entry
@@ -568,6 +572,11 @@ int tds_query_create(tds_index *ix, tds_query **out) {
             return fail(TDS_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
         }
     }
+    e = hipEventCreateWithFlags(&q->ev_wait, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        tds_query_destroy(q);
+        return fail(TDS_EDEVICE, "hipEventCreateWithFlags: %s", hipGetErrorString(e));
+    }
     ix->live_queries++;
     *out = q;
     return TDS_OK;
@@ -586,6 +595,7 @@ void tds_query_destroy(tds_query *q) {
     if (q->host_ctr) (void)hipHostFree(q->host_ctr);
     for (auto &ev : q->ev)
         if (ev) (void)hipEventDestroy(ev);
+    if (q->ev_wait) (void)hipEventDestroy(q->ev_wait);
     if (q->ix) q->ix->live_queries--;
     delete q;
 }
@@ -961,6 +971,12 @@ int tds_query_device_bytes(const tds_query *q, int64_t *bytes) {
 
 // Wait for the pending batch, re-run it on overflow, and fill the stats
 // (shared by the fetch calls). `who` names the caller in error messages.
+// Waits for the work the handle has enqueued so far on its stream.
+static hipError_t wait_own(tds_query *q) {
+    const hipError_t e = hipEventRecord(q->ev_wait, q->stream);
+    return e != hipSuccess ? e : hipEventSynchronize(q->ev_wait);
+}
+
 static int complete_batch(tds_query *q, const char *who) {
     hipStream_t st = q->stream;
     if (q->pending) {
@@ -968,7 +984,7 @@ static int complete_batch(tds_query *q, const char *who) {
             int rc = enqueue_emit(q, nullptr, 0);
             if (rc) return rc;
         }
-        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(wait_own(q));
         Counters c = *q->host_ctr;
         if (c.err) {
             q->pending = false;
@@ -1000,7 +1016,7 @@ static int complete_batch(tds_query *q, const char *who) {
             rc = enqueue_emit(q, nullptr, 0);
             if (rc) return rc;
             q->clear_needed = false;
-            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(wait_own(q));
             c = *q->host_ctr;
         }
         tds_stats &s = q->stats;
@@ -1074,7 +1090,7 @@ int tds_fetch_results(tds_query *q, tds_hit *out, int64_t cap, int32_t out_mem, 
                                        hipMemcpyDeviceToHost, st));
             // host output is complete on return (the early kernel finished
             // before the wait for the batch)
-            if (!direct || again) HIP_TRY(hipStreamSynchronize(st));
+            if (!direct || again) HIP_TRY(wait_own(q));
         }
         // device output is ordered on the batch's stream (fetch timing is
         // read by tds_query_stats)
@@ -1093,7 +1109,7 @@ static int copy_traj(tds_query *q, tds_traj_hit *out, int64_t cap, int32_t out_m
                                out_mem == TDS_MEM_HOST ? hipMemcpyDeviceToHost
                                                        : hipMemcpyDeviceToDevice,
                                q->stream));
-        if (out_mem == TDS_MEM_HOST) HIP_TRY(hipStreamSynchronize(q->stream));
+        if (out_mem == TDS_MEM_HOST) HIP_TRY(wait_own(q));
     }
     return TDS_OK;
 }
@@ -1170,7 +1186,7 @@ int tds_fetch_trajectories(tds_query *q, const int64_t *query_traj, int32_t traj
     // the record count to pinned host memory (after the handle's counters)
     long long *host_total = reinterpret_cast<long long *>(reinterpret_cast<char *>(q->host_ctr) + sizeof(Counters));
     HIP_TRY(hipMemcpyAsync(host_total, total_dev, sizeof(long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(wait_own(q));
     q->traj_total = *host_total;
     q->traj_valid = true;
     return copy_traj(q, out, cap, out_mem, n_total);
