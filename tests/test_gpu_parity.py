@@ -281,6 +281,27 @@ def test_host_query_validation():
         run(db, q.with_d(-1.0), 4, index=ix)
     with pytest.raises(tds.TdsError):
         run(db, q, 4, index=ix, block_size=96)
+    # host values are checked by the preparation kernel: the batch is
+    # accepted, its fetch reports the segment, and the handle then runs a
+    # valid batch (pageable and page-locked output)
+    qh = tds.Query(ix)
+    try:
+        for bad_d in (False, True):
+            bq = q.subset(np.arange(len(q)))
+            if bad_d:
+                bq = bq.with_d(1.0)
+                bq.d[len(bq) // 2] = -1.0
+            else:
+                bq.t1[2] = bq.t0[2]
+            qh.batch(bq, bq.d, mode="fp32_refine", tiling="range")
+            with pytest.raises(tds.TdsError) as e:
+                qh.fetch()
+            assert e.value.code == L.TDS_EINVAL and "invalid query segment" in str(e.value)
+            for out in ("host", "pinned"):
+                qh.batch(q, q.d, mode="fp32_refine", tiling="range")
+                compare(qh.fetch(out=out).sorted(), oracle.search(db, q), db, f"after error ({out})")
+    finally:
+        qh.close()
 
 
 def test_torch_allocator_hook():
