@@ -502,3 +502,35 @@ def test_bucket_offsets_in_and_beyond_lds(mode):
             compare(got, want, db, f"{tiling} m={m}")
         finally:
             ix.close()
+
+
+def test_partial_fetch_is_a_valid_subset():
+    # cap < number of hits: min(cap, n) records in an unspecified order, each
+    # one of the batch's hits with its interval, none twice; n_total is n;
+    # a later full fetch of the same batch returns every hit (device,
+    # pageable host and page-locked host output, both forms)
+    db, q = fx.dense_box(ntraj=200, L=30, box=4.0, nq=20, seed=43, d=1.5)
+    want = oracle.search(db, q)
+    n = len(want)
+    assert n > 300
+    key = {(int(a), int(b)): (ta, tb) for a, b, ta, tb in zip(want.q, want.e, want.ta, want.tb)}
+    ix = tds.build_index(db, 30)
+    qh = tds.Query(ix)
+    try:
+        for mode in ("fp64", "fp32_refine"):
+            for out in ("device", "host", "pinned"):
+                for cap in (0, 1, n // 3, n - 1):
+                    qh.batch(q, q.d, mode=mode, tiling="range")
+                    part = qh.fetch(out=out, cap=cap).numpy()
+                    label = f"{mode} {out} cap {cap}"
+                    assert len(part.query) == cap, label
+                    pairs = set(zip(part.query.tolist(), part.entry.tolist()))
+                    assert len(pairs) == cap, f"{label}: duplicate records"
+                    for a, b, ta, tb in zip(part.query, part.entry, part.ta, part.tb):
+                        wa, wb = key[(int(a), int(b))]
+                        assert abs(ta - wa) <= 1e-9 * max(1.0, abs(wa)), label
+                        assert abs(tb - wb) <= 1e-9 * max(1.0, abs(wb)), label
+                    compare(qh.fetch(out=out).sorted(), want, db, f"{label}, then in full")
+    finally:
+        qh.close()
+        ix.close()
