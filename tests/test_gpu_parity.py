@@ -534,3 +534,30 @@ def test_partial_fetch_is_a_valid_subset():
     finally:
         qh.close()
         ix.close()
+
+
+def test_two_handles_on_one_stream():
+    # each handle's fetch waits for its own work on the shared stream (an
+    # event after it), in either fetch order, with host and device output
+    import torch
+    db, q = fx.dense_box(ntraj=120, L=25, box=4.0, nq=16, seed=47, d=1.2)
+    q2 = q.with_d(0.6)
+    want1, want2 = oracle.search(db, q), oracle.search(db, q2)
+    ix = tds.build_index(db, 25)
+    s = torch.cuda.Stream()
+    ha, hb = tds.Query(ix), tds.Query(ix)
+    try:
+        for order in ("ab", "ba"):
+            for out in ("host", "device"):
+                ha.batch(q, q.d, mode="fp32_refine", tiling="range", stream=s)
+                hb.batch(q2, q2.d, mode="fp64", tiling="range", stream=s)
+                got = {}
+                for k in order:
+                    with torch.cuda.stream(s):
+                        got[k] = (ha if k == "a" else hb).fetch(out=out).sorted()
+                compare(got["a"], want1, db, f"handle a ({order}, {out})")
+                compare(got["b"], want2, db, f"handle b ({order}, {out})")
+    finally:
+        ha.close()
+        hb.close()
+        ix.close()
